@@ -1,0 +1,394 @@
+"""Pins of the CPU FP64 oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: each test checks a closed form, a
+textbook value, a brute-force enumeration, an invariance, or a library special
+case (NumPy's median / interp).  Citations are to QLP Data Release Notes 003.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2302_01293_amd import synth
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "constants.json")))
+
+
+# ---------------------------------------------------------------------------
+# Physical closed forms (Sec. 2.1: Keplerian durations, minimum period at a/R*)
+# ---------------------------------------------------------------------------
+def test_kepler_period_of_the_earth(oracle):
+    # a = 1 AU around one solar density star of solar radius is the Earth's orbit:
+    # the period at a/R* = AU/R_sun must be the sidereal year.
+    e = GOLD["earth"]
+    aor = e["au_m"] / GOLD["iau_2015_nominal"]["R_sun_m"]
+    P = oracle.period_at_a(aor, 1.0)
+    assert abs(P / e["sidereal_year_days"] - 1.0) < 1e-5
+
+
+def test_circular_duration_of_the_earth(oracle):
+    # Central transit of the Earth seen from afar: about 13 hours (textbook).
+    P = GOLD["earth"]["sidereal_year_days"]
+    dur_h = oracle.qcirc(1.0 / P, 1.0) * P * 24.0
+    assert 12.9 < dur_h < 13.05
+    # small-angle (P/pi)(R/a) against the exact arcsin form: equal to 1e-5 at 215 R*
+    aor = GOLD["earth"]["au_m"] / GOLD["iau_2015_nominal"]["R_sun_m"]
+    exact_h = P / math.pi * math.asin(1.0 / aor) * 24.0
+    assert abs(dur_h / exact_h - 1.0) < 1e-5
+
+
+def test_duty_cycle_matches_kepler_inversion(oracle):
+    # q_circ(f) = (1/pi) R*/a with a from Kepler III: invert period_at_a by bisection.
+    for f, rho in [(1.0, 1.0), (0.1, 0.3), (2.5, 7.0)]:
+        lo, hi = 1.0, 1e4
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if oracle.period_at_a(mid, rho) < 1.0 / f:
+                lo = mid
+            else:
+                hi = mid
+        assert abs(oracle.qcirc(f, rho) / ((1.0 / math.pi) / lo) - 1.0) < 1e-12
+
+
+def test_period_scaling_laws(oracle):
+    p1 = oracle.period_at_a(2.0, 1.0)
+    assert abs(oracle.period_at_a(2.0, 4.0) / (p1 / 2.0) - 1.0) < 1e-15      # P ~ rho^-1/2
+    assert abs(oracle.period_at_a(8.0, 1.0) / (p1 * 8.0) - 1.0) < 1e-15      # P ~ a^3/2
+    assert abs(oracle.period_at_a(2.0, float("nan")) - p1) == 0.0            # missing -> solar
+    assert abs(oracle.period_at_a(2.0, -1.0) - p1) == 0.0
+    # survey-derived values at a = 2, 3 R* (solar density)
+    assert abs(p1 - 0.327634) < 2e-6
+    assert abs(oracle.period_at_a(3.0, 1.0) - 0.601901) < 2e-6
+
+
+def test_qcirc_scaling(oracle):
+    q = oracle.qcirc(1.0, 1.0)
+    assert abs(oracle.qcirc(8.0, 1.0) / (4.0 * q) - 1.0) < 1e-14   # f^(2/3)
+    assert abs(oracle.qcirc(1.0, 8.0) / (q / 2.0) - 1.0) < 1e-14   # rho^(-1/3)
+
+
+# ---------------------------------------------------------------------------
+# Durations, grid and bins (Sec. 2.1 footnote)
+# ---------------------------------------------------------------------------
+def test_duration_ladder(oracle):
+    m = oracle.durations()
+    assert list(m) == list(range(3, 13))
+    # m = noverlap fine bins is the shortest duration (0.5 q_circ), 4x that the longest (2.0 q_circ)
+    sp = GOLD["search_parameters"]
+    assert m[0] == sp["noverlap"]
+    assert m[-1] / m[0] == sp["duration_max_over_circular"] / sp["duration_min_over_circular"]
+    # a finer ladder keeps the same ends
+    m2 = oracle.durations(oracle.params(dlogq=0.05))
+    assert m2[0] == 3 and m2[-1] == 12
+
+
+def test_grid_properties(oracle):
+    b = synth.config0()
+    t, y, w = b.star(0)
+    p = oracle.params()
+    f, nb, bd = oracle.grid(t, w, 1.0, p, pmin=0.5, pmax=13.7)
+    T = bd.T
+    assert abs(f[0] * 13.7 - 1.0) < 1e-14
+    assert f[-1] <= (1.0 / 0.5) * (1 + 1e-14)
+    # the next grid point would pass 1/Pmin
+    u_next = bd.umin + len(f) * bd.A
+    assert u_next ** 3 > 2.0 * (1 - 1e-14)
+    # spacing: each step shifts the phase at the end of the baseline by
+    # q_lo / spp (samples_per_peak), up to O(A/u)
+    qlo = np.array([0.5 * oracle.qcirc(x, 1.0) for x in f[:-1]])
+    ratio = np.diff(f) * 2.0 * T / qlo
+    assert ratio.min() >= 1.0 - 1e-9
+    assert ratio.max() <= 1.0 + 3.5 * bd.A / bd.umin
+    # fine bins: width 1/nb <= q_lo/noverlap, and one bin fewer would be too wide
+    qlo_all = np.array([0.5 * oracle.qcirc(x, 1.0) for x in f])
+    assert np.all(1.0 / nb <= qlo_all / 3.0 * (1 + 1e-12))
+    assert np.all(1.0 / (nb - 1) > qlo_all / 3.0 * (1 - 1e-12))
+    assert nb.max() == 455 and nb.min() == 50
+
+
+def test_pmax_rule(oracle):
+    p = oracle.params()
+    # one stretch of 20 d with no gap > 27.4 d: half of it
+    t = np.concatenate([np.arange(0, 20.0, 0.1), np.arange(40.0, 60.0, 0.1)])
+    st, b = oracle.bounds(t, None, 1.0, p)
+    assert st == 0 and abs(b.pmax - (t[-1] - t[0]) / 2) < 1e-12
+    # a 30-day gap splits the data: the longest stretch
+    t = np.concatenate([np.arange(0, 20.0, 0.1), np.arange(50.0, 60.0, 0.1)])
+    st, b = oracle.bounds(t, None, 1.0, p)
+    assert st == 0 and abs(b.pmax - (np.arange(0, 20.0, 0.1)[-1])) < 1e-12
+    # zero weights are ignored for the baseline and the stretches
+    w = np.ones_like(t)
+    w[t > 45] = 0.0
+    st, b = oracle.bounds(t, w, 1.0, p)
+    assert st == 0 and abs(b.T - np.arange(0, 20.0, 0.1)[-1]) < 1e-12
+    # Pmin >= Pmax: empty grid
+    st, b = oracle.bounds(np.arange(0, 0.5, 0.01), None, 1.0, p)
+    assert st == -3
+    # cfg0's 27.4-d sector: Pmax ~ 13.7 d
+    t0 = synth.config0().star(0)[0]
+    st, b = oracle.bounds(t0, None, 1.0, p)
+    assert abs(b.pmax - 13.7) < 0.02
+
+
+def test_sturges(oracle):
+    # N = round(1 + 3.322 log10 n) (Sec. 2.2 footnote)
+    assert oracle.sturges(3658) == 13
+    assert oracle.sturges(1000) == 11
+    assert oracle.sturges(4489) == 13
+    assert oracle.sturges(148001) == 18
+    assert oracle.sturges(1) == 1
+    assert oracle.sturges(2) == 2
+
+
+# ---------------------------------------------------------------------------
+# BLS statistic: brute force, closed forms and invariances
+# ---------------------------------------------------------------------------
+def _window_sums_direct(t, y, w, f, nb, m, j, t0):
+    """Sum wt and wt*x over the points whose fine bin lies in [j, j+m) mod nb."""
+    W = w.sum()
+    wt = w / W
+    x = y - np.sum(wt * y)
+    ph = (t - t0) * f
+    ph = ph - np.floor(ph)
+    b = np.minimum(nb - 1, np.floor(ph * nb).astype(np.int64))
+    inwin = ((b - j) % nb) < m
+    return wt[inwin].sum(), (wt * x)[inwin].sum()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_bruteforce_windows(oracle, seed):
+    b = synth.tiny(24, seed=seed, span=3.0)
+    t, y, w = b.star(0)
+    sp = oracle.bls_star(t, y, w, 1.0, pmin=0.4, pmax=1.5)
+    M = oracle.durations()
+    for i in np.linspace(0, len(sp.f) - 1, 7).astype(int):
+        f, nb = sp.f[i], sp.nb[i]
+        best, bm, bj = -1.0, 0, -1
+        for m in M:
+            if m >= nb:
+                continue
+            for j in range(nb):
+                r, s = _window_sums_direct(t, y, w, f, nb, m, j, sp.bounds.t0)
+                if 0 < r < 1:
+                    p2 = s * s / (r * (1 - r))
+                    if p2 > best * (1 + 1e-12):
+                        best, bm, bj = p2, m, j
+        assert abs(sp.sr[i] - math.sqrt(best)) <= 1e-12 * math.sqrt(best)
+        assert (sp.m[i], sp.j[i]) == (bm, bj)
+
+
+def _runs_max(t, y, w, f, t0, nmax=None):
+    """Kovacs' unbinned search: every cyclic run of phase-sorted points."""
+    W = w.sum()
+    wt = w / W
+    x = y - np.sum(wt * y)
+    ph = ((t - t0) * f) % 1.0
+    o = np.argsort(ph, kind="stable")
+    wt, v = wt[o], (wt * x)[o]
+    N = len(t)
+    best = 0.0
+    for a in range(N):
+        r = s = 0.0
+        for k in range(1, (nmax or N - 1) + 1):
+            q = (a + k - 1) % N
+            r += wt[q]
+            s += v[q]
+            if 0 < r < 1 - 1e-15:
+                best = max(best, s * s / (r * (1 - r)))
+    return math.sqrt(best)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_binned_below_unbinned_runs(oracle, seed):
+    b = synth.tiny(20, seed=seed, span=2.0)
+    t, y, w = b.star(0)
+    sp = oracle.bls_star(t, y, w, 1.0, pmin=0.4, pmax=1.0)
+    for i in np.linspace(0, len(sp.f) - 1, 9).astype(int):
+        assert sp.sr[i] <= _runs_max(t, y, w, sp.f[i], sp.bounds.t0) * (1 + 1e-12)
+
+
+def test_binned_equals_runs_one_point_per_bin(oracle):
+    # One point per fine bin (the first at phase 0, the others at bin centres, in
+    # random cycles): a run of k phase-sorted points is then the same set as a
+    # k-bin window, so SR equals the maximum over cyclic runs of lengths in the ladder.
+    rng = np.random.default_rng(5)
+    pmax = 1.3
+    f_probe, nb_probe, _ = oracle.grid(np.array([0.0, 10.0]), None, 1.0, oracle.params(), pmin=0.4, pmax=pmax)
+    f0, nb0 = f_probe[0], int(nb_probe[0])
+    T0 = synth.T_OFFSET
+    k = np.arange(1, nb0)
+    t = np.concatenate([[T0], T0 + (rng.integers(0, 3, nb0 - 1) + (k + 0.5) / nb0) / f0])
+    t = np.sort(t)
+    y = 1.0 + rng.normal(0, 1e-3, nb0)
+    w = rng.uniform(0.5, 2.0, nb0)
+    sp = oracle.bls_star(t, y, w, 1.0, pmin=0.4, pmax=pmax)
+    assert sp.f[0] == f0 and sp.nb[0] == nb0
+    wt = w / w.sum()
+    x = y - np.sum(wt * y)
+    ph = ((t - t[0]) * f0) % 1.0
+    ordr = np.argsort(ph)
+    assert np.array_equal(np.floor(ph[ordr] * nb0).astype(int), np.arange(nb0))
+    M = set(oracle.durations().tolist())
+    best = 0.0
+    for a0 in range(nb0):
+        r = s = 0.0
+        for kk in range(1, max(M) + 1):
+            q = ordr[(a0 + kk - 1) % nb0]
+            r += wt[q]
+            s += wt[q] * x[q]
+            if kk in M and 0 < r < 1:
+                best = max(best, s * s / (r * (1 - r)))
+    assert abs(sp.sr[0] - math.sqrt(best)) <= 1e-12 * math.sqrt(best)
+
+
+def _aligned_box(oracle, m_true=6, depth=2e-3, dense=40):
+    """Noiseless light curve whose box covers exactly fine bins [j0, j0+m) at a grid frequency."""
+    t = synth.sector_times([0], synth.CADENCE_30MIN / 4)
+    st, bd = oracle.bounds(t, None, 1.0, oracle.params(), pmin=0.5, pmax=13.7)
+    f, nb, _ = oracle.grid(t, None, 1.0, oracle.params(), pmin=0.5, pmax=13.7)
+    i = int(np.argmin(np.abs(1.0 / f - 3.1)))
+    fi, nbi = f[i], nb[i]
+    j0 = 17
+    ph = (t - bd.t0) * fi
+    ph = ph - np.floor(ph)
+    b = np.minimum(nbi - 1, np.floor(ph * nbi).astype(int))
+    intr = ((b - j0) % nbi) < m_true
+    y = np.ones_like(t)
+    y[intr] -= depth
+    return t, y, i, fi, nbi, j0, intr
+
+
+def test_noiseless_box_closed_form(oracle):
+    m_true, depth = 6, 2e-3
+    t, y, i, fi, nbi, j0, intr = _aligned_box(oracle, m_true, depth)
+    sp = oracle.bls_star(t, y, None, 1.0, pmin=0.5, pmax=13.7)
+    r = intr.mean()
+    expect = depth * math.sqrt(r * (1 - r))
+    assert abs(sp.sr[i] - expect) <= 1e-12 * expect
+    assert (sp.m[i], sp.j[i]) == (m_true, j0)
+    assert abs(-sp.s[i] / (sp.r[i] * (1 - sp.r[i])) - depth) <= 1e-12 * depth
+    # the maximum over the grid is this value (other frequencies fold to equal or lower)
+    assert sp.sr.max() <= expect * (1 + 1e-12)
+    top = np.nonzero(sp.sr >= expect * (1 - 1e-12))[0]
+    assert i in top
+    # S/N picks a frequency of the tie set holding the injection
+    snr, tr, res = oracle.snr(sp.f, sp.sr)
+    assert res.i_snr in top and res.snr_max > 9
+
+
+@pytest.mark.parametrize("kind", ["offset", "pow2", "scale3", "shift"])
+def test_invariances(oracle, kind):
+    b = synth.ragged(3, start=0)
+    t, y, w = b.star(1)
+    pr = dict(rho=float(b.rho[1]), pmin=0.6, pmax=6.0)
+    base = oracle.bls_star(t, y, w, **pr)
+    if kind == "offset":
+        other = oracle.bls_star(t, y + 0.37, w, **pr)
+        np.testing.assert_allclose(other.sr, base.sr, rtol=1e-9, atol=0)
+    elif kind == "pow2":
+        other = oracle.bls_star(t, y, w * 8.0, **pr)
+        assert np.array_equal(other.sr, base.sr)
+    elif kind == "scale3":
+        other = oracle.bls_star(t, y, w * 3.0, **pr)
+        np.testing.assert_allclose(other.sr, base.sr, rtol=1e-12, atol=0)
+    else:
+        other = oracle.bls_star(t + 1024.0, y, w, **pr)
+        assert np.array_equal(other.sr, base.sr)
+        assert other.bounds.t0 == base.bounds.t0 + 1024.0
+
+
+def test_config0_recovers_injection(oracle):
+    b = synth.config0()
+    out = oracle.batch(b.t, b.y, b.w, b.offsets, b.rho, b.pmin, b.pmax)
+    R = dict(zip(oracle.RESULT_FIELDS, out["results"][0]))
+    assert abs(R["period"] / 3.1 - 1) < 0.01
+    assert R["snr"] > 9
+    assert abs(R["depth"] / 2e-3 - 1) < 0.2
+    assert abs(R["duration"] / b.truth["duration"][0] - 1) < 0.25
+
+
+# ---------------------------------------------------------------------------
+# S/N (Sec. 2.2 item 1): library special case and exact invariants
+# ---------------------------------------------------------------------------
+def _numpy_snr(f, sr):
+    n = len(f)
+    nb = int(math.floor(1 + 3.322 * math.log10(n) + 0.5))
+    span = f[-1] - f[0]
+    k = np.minimum(nb - 1, np.floor((f - f[0]) / span * nb).astype(int))
+    xs, ys = [], []
+    for q in range(nb):
+        sel = sr[k == q]
+        if len(sel):
+            xs.append(f[0] + (q + 0.5) * span / nb)
+            ys.append(np.median(sel))
+    trend = np.interp(f, xs, ys)
+    rho = sr - trend
+    sigma = 1.4826 * np.median(np.abs(rho - np.median(rho)))
+    return rho / sigma, trend, sigma
+
+
+def test_snr_numpy_special_case(oracle):
+    b = synth.config0()
+    sp = oracle.bls_star(*b.star(0), 1.0, pmin=0.5, pmax=13.7)
+    snr, tr, res = oracle.snr(sp.f, sp.sr)
+    snr_np, tr_np, sig_np = _numpy_snr(sp.f, sp.sr)
+    np.testing.assert_allclose(tr, tr_np, rtol=1e-13, atol=1e-18)
+    assert abs(res.sigma / sig_np - 1) < 1e-12
+    np.testing.assert_allclose(snr, snr_np, rtol=1e-9, atol=1e-9)
+    assert res.i_snr == int(np.argmax(snr_np))
+    assert res.nbins_sturges == 13
+
+
+def test_snr_invariants(oracle):
+    rng = np.random.default_rng(7)
+    f = np.sort(rng.uniform(0.1, 2.0, 777))
+    sr = 1e-4 * (1 + 3 * np.exp(-f)) + rng.gamma(2.0, 1e-5, 777)
+    sr[400] += 5e-4
+    s1, _, r1 = oracle.snr(f, sr)
+    s2, _, r2 = oracle.snr(f, 3.5 * sr + 0.25)
+    np.testing.assert_allclose(s1, s2, rtol=1e-8, atol=1e-8)
+    assert r1.i_snr == r2.i_snr == 400
+    # median |S/N - median S/N| = 1/1.4826 by construction
+    assert abs(np.median(np.abs(s1 - np.median(s1))) - 1 / 1.4826) < 1e-12
+
+
+def test_snr_constant_plus_spike(oracle):
+    f = np.linspace(0.1, 3.0, 1001)
+    sr = np.full(1001, 2e-4)
+    sr[::2] += 1e-6  # alternate so the MAD is non-zero
+    sr[500] = 1e-3
+    snr, tr, res = oracle.snr(f, sr)
+    assert res.i_snr == 500
+    assert np.all((tr >= 2e-4) & (tr <= 2e-4 + 1e-6))
+
+
+def test_snr_linear_trend_through_knots(oracle):
+    # SR constant inside each Sturges bin, equal to a line at the bin centre: every
+    # bin median is that value, so the interpolated trend is the line itself between
+    # the first and last knot, and is held constant beyond them.
+    f = np.linspace(0.1, 3.0, 1001)
+    nb = oracle.sturges(len(f))
+    span = f[-1] - f[0]
+    k = np.minimum(nb - 1, np.floor((f - f[0]) / span * nb).astype(int))
+    centre = f[0] + (k + 0.5) * span / nb
+    line = lambda x: 1e-4 + 2e-5 * x
+    sr = line(centre)
+    snr, tr, res = oracle.snr(f, sr)
+    half = 0.5 * span / nb
+    inner = (f >= f[0] + half) & (f <= f[-1] - half)
+    np.testing.assert_allclose(tr[inner], line(f[inner]), rtol=1e-12)
+    assert np.all(tr[f < f[0] + half] == line(f[0] + half))
+    assert np.all(tr[f > f[-1] - half] == line(f[-1] - half))
+
+
+def test_snr_zero_sigma(oracle):
+    f = np.linspace(0.1, 3.0, 500)
+    snr, tr, res = oracle.snr(f, np.full(500, 3e-4))
+    assert res.status == 1 and np.all(snr == 0) and res.sigma == 0.0
+
+
+def test_median_even_count(oracle):
+    assert oracle.median([4.0, 1.0, 3.0, 2.0]) == 2.5
+    assert oracle.median([5.0, 1.0, 3.0]) == 3.0
