@@ -1,0 +1,193 @@
+/*
+ * mi355bls.h — C ABI of the MI355X (gfx950) Box Least Squares transit search.
+ *
+ * The library computes, for many light curves at once, the Box Least Squares
+ * periodogram of Kovacs, Zucker & Mazeh (2002) on a per-star Keplerian
+ * frequency grid, followed by the spectroscopic S/N post-processing of QLP Data
+ * Release Notes 003 (Kunimoto et al. 2023):
+ *   - search grid and durations: Sec. 2.1 and its footnote (Keplerian duration
+ *     window 0.5-2.0 x the circular-orbit duration at the star's density,
+ *     samples_per_peak = 2, dlogq = 0.1, noverlap = 3);
+ *   - period bounds: Sec. 2.1 (a = 2 R* or 3 R* for the minimum period; the
+ *     longest continuous stretch, or half of it without gaps longer than a
+ *     sector, for the maximum);
+ *   - S/N: Sec. 2.2 item 1, Eq. 1 with its two changes (Sturges-rule
+ *     median-binned trend; sigma = 1.4826 x MAD).
+ *
+ * Conventions
+ *   - Every function returns a bls_status (0 = success, < 0 = error).  No C++
+ *     exception crosses the ABI.  bls_status_string() names a code.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *     memory of the current device.  The caller owns every buffer it passes.
+ *   - A plan owns host-side descriptors only.  Device state lives in a caller
+ *     allocated workspace of bls_plan_query(...)->workspace_bytes bytes, filled by
+ *     bls_plan_upload().  bls_search_batch() and bls_snr() allocate nothing, never
+ *     synchronise the host and only enqueue work on the given stream, so they can
+ *     be captured into a HIP graph.  A plan and its workspace serve one stream at
+ *     a time.
+ *   - Light curves are packed back to back ("ragged CSR"): star s owns points
+ *     [off_s, off_s + n_points_s) of the t/y/w arrays, off_0 = 0.  Times are in
+ *     days, ascending within a star; flux is unitless; weights are 1/sigma^2 (>= 0,
+ *     points with w = 0 contribute nothing and are ignored for the baseline).
+ *   - Per-frequency outputs of all stars are packed the same way, star s owning
+ *     [freq_offsets[s], freq_offsets[s+1]) (bls_plan_query).
+ */
+#ifndef MI355BLS_H
+#define MI355BLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* bls_stream_t; /* a hipStream_t; NULL = default stream */
+
+typedef int32_t bls_status;
+enum {
+  BLS_OK = 0,
+  BLS_E_ARG = -1,         /* invalid argument (NULL pointer, bad size or parameter) */
+  BLS_E_INPUT = -2,       /* invalid light curve: non-finite value, w < 0, times not
+                             ascending, fewer than 2 weighted points, zero total weight */
+  BLS_E_EMPTY_GRID = -3,  /* Pmin >= Pmax for a star: nothing to search */
+  BLS_E_NOMEM = -4,       /* host allocation failed */
+  BLS_E_HIP = -5,         /* a HIP call failed (launch or copy) */
+  BLS_E_STATE = -6,       /* workspace missing, too small or not uploaded */
+  BLS_E_UNSUPPORTED = -7  /* a star exceeds a compiled limit (see bls_limits) */
+};
+
+/* Search parameters.  bls_default_params() fills the paper's values (Sec. 2.1,
+ * its footnote, and Sec. 2.2). */
+typedef struct bls_params {
+  double spp;          /* samples per peak of the frequency grid (2) */
+  double qmin_fac;     /* shortest duration / circular duration (0.5) */
+  double qmax_fac;     /* longest duration / circular duration (2.0) */
+  double dlogq;        /* natural-log spacing of the duration ladder (0.1) */
+  int32_t noverlap;    /* shifted bin sets per shortest duration (3) */
+  int32_t dip_only;    /* 0: windows of either sign count (Kovacs s^2); 1: s < 0 only */
+  int32_t mad_of_raw;  /* 0: sigma from the MAD of the detrended SR (default);
+                          1: from the MAD of raw SR */
+  int32_t precision;   /* 0: FP64 phase and FP64-exact sums (plain path);
+                          1: FP64 phase, FP32 compensated bin sums (fast path) */
+  double a_min_rstar;  /* minimum a/R*: 2 (Sectors 61+) or 3 (Sectors 59-60) */
+  double sector_days;  /* gap length that splits continuous stretches (27.4) */
+} bls_params;
+
+/* Per-star inputs. */
+typedef struct bls_star {
+  int64_t n_points;    /* points of this star in the packed arrays (>= 2) */
+  double rho_solar;    /* stellar density in solar units; NaN or <= 0 means solar */
+  double pmin_days;    /* > 0 overrides the minimum period (else a = a_min_rstar) */
+  double pmax_days;    /* > 0 overrides the maximum period (else from the stretches) */
+} bls_star;
+
+/* Best window at one frequency: m bins starting at fine bin j (start phase j/nb);
+ * r = in-window weight fraction, s = in-window sum of w~ (y - ybar).
+ * m = 0, j = -1 when no window is valid (then SR = 0). */
+typedef struct bls_best {
+  int32_t m, j;
+  double r, s;
+} bls_best;
+
+/* Per-star summary written by bls_snr(). */
+typedef struct bls_result {
+  int64_t i_snr;       /* frequency index (within the star) of the maximum S/N */
+  int64_t i_sr;        /* frequency index of the maximum SR */
+  double period;       /* 1 / f at i_snr, days */
+  double t0;           /* mid-time of the best window at i_snr (first after the
+                          star's first weighted time), days; NaN without d_best */
+  double duration;     /* (m / nb) / f, days; NaN without d_best */
+  double depth;        /* -s / (r (1 - r)), positive for a dip; NaN without d_best */
+  double sr;           /* SR at i_snr */
+  double snr;          /* S/N at i_snr */
+  double trend;        /* median-binned trend at i_snr */
+  double sigma;        /* 1.4826 x MAD */
+  int32_t status;      /* 0 ok; 1 sigma = 0 (S/N set to 0) */
+  int32_t nbins;       /* Sturges bin count used for the trend */
+} bls_result;
+
+typedef struct bls_plan bls_plan;
+
+/* Fill *p with the paper's parameters. */
+bls_status bls_default_params(bls_params* p);
+
+/* Build a plan for n_stars light curves (host work only, synchronous).
+ * t_host: packed times [sum n_points] (required).  y_host, w_host: packed
+ * fluxes and weights (nullable: NULL skips the flux check / means unit weights);
+ * they must equal the device arrays later given to bls_search_batch().
+ * Validates every star (BLS_E_INPUT, BLS_E_EMPTY_GRID), then derives per star the
+ * baseline, the period bounds (Sec. 2.1), the frequency grid (uniform in f^(1/3),
+ * spacing 1/spp of the shortest searched duration over the baseline) and the
+ * work schedule.  On error *out is NULL and *bad_star (nullable) names the star. */
+bls_status bls_plan_create(const bls_params* p, int32_t n_stars, const bls_star* stars,
+                           const double* t_host, const double* y_host, const double* w_host,
+                           bls_plan** out, int32_t* bad_star);
+
+/* Sizes of a plan.  n_freq_total: frequencies of all stars.  freq_offsets_host
+ * (nullable) receives n_stars + 1 prefix offsets.  workspace_bytes: device bytes the
+ * caller must allocate (256-byte aligned) and pass to upload/search/snr. */
+bls_status bls_plan_query(const bls_plan* plan, int64_t* n_freq_total, int64_t* freq_offsets_host,
+                          int64_t* workspace_bytes);
+
+/* Per-star description: out[0..9] = t0, T, pmin, pmax, krho (circular duty cycle
+ * coefficient, q = krho f^(2/3)), umin, A (grid: f_i = (umin + i A)^3), nf,
+ * nb_max, sturges bins. */
+bls_status bls_plan_star_info(const bls_plan* plan, int32_t star, double* out10);
+
+/* Frequencies (1/day) and fine-bin counts of one star's grid, exactly as the
+ * device computes them (f_host [nf], nb_host [nf], both host, nullable). */
+bls_status bls_plan_frequencies(const bls_plan* plan, int32_t star, double* f_host, int32_t* nb_host);
+
+/* The fine-bin duration ladder: writes up to cap lengths, returns the count
+ * through *n. */
+bls_status bls_plan_durations(const bls_plan* plan, int32_t* m_host, int32_t cap, int32_t* n);
+
+/* Copy the plan's descriptors into the device workspace (enqueued on stream;
+ * the host copy stays owned by the plan, which must outlive the copy). */
+bls_status bls_plan_upload(bls_plan* plan, void* d_workspace, int64_t workspace_bytes,
+                           bls_stream_t stream);
+
+/* Preparation of a batch (the normalisation of Kovacs et al. 2002 as used in
+ * Sec. 2.2 item 1): per star W = sum w, wt = w / W, ybar = sum wt y (compensated
+ * sums), x = y - ybar; then dt = t - t0 and the exclusive prefix sums of wt and of
+ * wt x in int64 fixed point, stored in the workspace.  Device inputs: packed t, y
+ * (required) and w (nullable: unit weights), identical to the host arrays given to
+ * bls_plan_create().  Must precede bls_search_batch() on the same stream. */
+bls_status bls_prepare(bls_plan* plan, void* d_workspace, const double* d_t, const double* d_y,
+                       const double* d_w, bls_stream_t stream);
+
+/* BLS search (Kovacs statistic on the Sec. 2.1 grid) over prepared data.  For every
+ * frequency: phase-fold, fine-bin sums, every window of m fine bins (m in the
+ * duration ladder) starting at every fine bin; SR = sqrt(max s^2 / (r (1 - r))) over
+ * windows with m < nb and 0 < r < 1 (and s < 0 if dip_only), ties to the smallest
+ * (m, j).  Outputs (device, caller-owned):
+ *   d_sr   [n_freq_total]  SR per frequency;
+ *   d_best [n_freq_total]  best window per frequency (nullable).
+ * d_windows (nullable) restricts the search to n_windows triples
+ * (star, i_begin, i_end) of int64 (device); frequencies outside them are not
+ * written.  NULL searches every star's full grid. */
+bls_status bls_search_batch(bls_plan* plan, void* d_workspace, const int64_t* d_windows,
+                            int64_t n_windows, double* d_sr, bls_best* d_best, bls_stream_t stream);
+
+/* Spectroscopic S/N (Sec. 2.2 item 1, Eq. 1 with the median-binned trend and the
+ * MAD-based sigma).  d_sr: SR of every frequency (device).  d_best (nullable) feeds
+ * t0/duration/depth of the result.  d_snr (nullable, device [n_freq_total]) gets
+ * S/N per frequency.  d_result (device [n_stars]) gets the summary. */
+bls_status bls_snr(bls_plan* plan, void* d_workspace, const double* d_sr, const bls_best* d_best,
+                   double* d_snr, bls_result* d_result, bls_stream_t stream);
+
+/* Release a plan (host memory only). */
+void bls_plan_destroy(bls_plan* plan);
+
+/* Static text naming a status code. */
+const char* bls_status_string(bls_status s);
+
+/* Compiled limits: out[0] = maximum fine bins per frequency, out[1] = maximum
+ * duration-ladder length, out[2] = maximum points per star. */
+bls_status bls_limits(int64_t* out3);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MI355BLS_H */

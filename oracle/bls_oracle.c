@@ -77,9 +77,11 @@ enum { ORC_OK = 0, ORC_E_ARG = -1, ORC_E_INPUT = -2, ORC_E_EMPTY = -3 };
 /* that follows it reproduces the same bits.                                   */
 /* ------------------------------------------------------------------------- */
 double orc_k_sun(void) {
-  double r3 = (ORC_R_SUN * ORC_R_SUN) * ORC_R_SUN;
-  double num = cbrt((((4.0 * ORC_PI) * ORC_PI) * r3) / ORC_GM_SUN);
-  return num / (ORC_PI * cbrt(ORC_DAY * ORC_DAY));
+  /* volatile: evaluate with the C library at run time (no compile-time folding) */
+  volatile double rs = ORC_R_SUN, gm = ORC_GM_SUN, day = ORC_DAY, pi = ORC_PI;
+  double r3 = (rs * rs) * rs;
+  double num = cbrt((((4.0 * pi) * pi) * r3) / gm);
+  return num / (pi * cbrt(day * day));
 }
 
 /* Density in solar units; missing (NaN or <= 0) means solar (Sec. 2.1). */
@@ -89,7 +91,8 @@ double orc_krho(double rho) { return orc_k_sun() / cbrt(orc_rho(rho)); }
 
 /* Period at which a = a_min R* for density rho (Kepler III), in days (Sec. 2.1). */
 double orc_period_at_a(double a_min, double rho) {
-  double r3 = (ORC_R_SUN * ORC_R_SUN) * ORC_R_SUN;
+  volatile double rs = ORC_R_SUN;
+  double r3 = (rs * rs) * rs;
   double a3 = (a_min * a_min) * a_min;
   return ((2.0 * ORC_PI) * sqrt((a3 * r3) / (ORC_GM_SUN * orc_rho(rho)))) / ORC_DAY;
 }

@@ -1,0 +1,86 @@
+// plan.hpp — host-side plan and device descriptor layouts of the MI355X BLS library.
+//
+// The plan turns the paper's problem statement (times, fluxes, weights, stellar
+// density and period bounds; QLP Data Release Notes 003 Sec. 2.1) into per-star
+// grid descriptors and a cost-ordered list of work items.  The frequency grid is
+// never materialised: the device recomputes f_i = (umin + i A)^3 and the fine-bin
+// count nb_i = ceil(noverlap / (kq (umin + i A)^2)) from four numbers per star,
+// with the same IEEE operations as the host (no FMA contraction anywhere).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "mi355bls.h"
+
+namespace mi355bls {
+
+// Compiled limits.
+constexpr int kThreads = 1024;        // threads per search / prep / S/N workgroup
+constexpr int kUMax = 12;             // register-resident points per thread
+constexpr int kGBytes = 128 * 1024;   // LDS bytes for the per-frequency accumulators
+constexpr int kNbLimit = kGBytes / 16;  // largest fine-bin count (one frequency per group)
+constexpr int kFMax = 32;             // most frequencies processed together
+constexpr int kMCap = 32;             // longest duration (in fine bins)
+constexpr int64_t kMaxPoints = int64_t(1) << 30;
+constexpr int kMaxSturges = 64;
+
+// Per-star descriptor (device copy is read-only).
+struct StarDesc {
+  int64_t p_off;    // first point in the packed arrays
+  int64_t n;        // points
+  int64_t f_off;    // first frequency in the packed per-frequency outputs
+  int64_t nf;       // frequencies
+  double t0;        // first time with w > 0 (phase origin)
+  double umin;      // grid start in u = f^(1/3)
+  double A;         // grid step in u
+  double kq;        // qmin_fac * krho: q_lo(f) = kq f^(2/3)
+  int32_t nb0;      // fine bins at i = 0 (the largest of the star)
+  int32_t sturges;  // Sturges bin count of the S/N trend
+  int32_t pad0, pad1;
+  double T, pmin, pmax, krho;  // descriptive (host queries)
+};
+static_assert(sizeof(StarDesc) == 112, "StarDesc layout");
+
+// Per-star values written by the preparation kernel.
+struct StarRt {
+  int64_t cw_total;  // sum of fixed-point weights (units of 2^-62)
+  int64_t cs_total;  // sum of fixed-point weighted residuals (units of s_scale)
+  double s_scale;    // 2^-e: value of one unit of the residual fixed point
+  double pad;
+};
+
+// A work item: frequencies [i0, i1) of one star.
+struct WorkItem {
+  int32_t star, i0, i1, pad;
+};
+
+// Scalars shared by every kernel of a plan.
+struct Consts {
+  int32_t noverlap;
+  int32_t dip_only;
+  int32_t mad_of_raw;
+  int32_t m_max;       // longest duration in bins
+  uint32_t m_mask;     // bit (m-1) set for every duration m of the ladder
+  int32_t pad;
+};
+
+struct Layout {  // byte offsets inside the device workspace
+  int64_t stars, rt, items, dt, cw, cs, rho, total;
+};
+
+}  // namespace mi355bls
+
+struct bls_plan {
+  bls_params params;
+  int32_t n_stars = 0;
+  int64_t n_points = 0;
+  int64_t n_freq = 0;
+  std::vector<mi355bls::StarDesc> stars;
+  std::vector<mi355bls::WorkItem> items;
+  std::vector<int64_t> freq_offsets;
+  std::vector<int32_t> durations;
+  mi355bls::Consts consts{};
+  mi355bls::Layout layout{};
+  void* uploaded_to = nullptr;  // workspace the descriptors were copied into
+};

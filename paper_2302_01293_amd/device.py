@@ -1,0 +1,84 @@
+"""Device-side driver: PyTorch tensors for HBM buffers and streams, the C ABI for work.
+
+``DeviceSearch`` owns the device copies of one packed batch, the plan's workspace
+and the output buffers, and enqueues ``bls_search_batch`` + ``bls_snr`` on the
+current PyTorch stream.  Nothing here computes any part of the search.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BEST_DTYPE, RESULT_DTYPE, Plan
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class DeviceSearch:
+    """Plain BLS + S/N over a packed batch resident in HBM."""
+
+    def __init__(self, t, y, w, offsets, rho=None, pmin=None, pmax=None, params=None,
+                 device: str = "cuda", want_snr: bool = True, want_best: bool = True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("DeviceSearch needs a GPU (HIP device)")
+        self.plan = Plan(t, y, w, offsets, rho, pmin, pmax, params)
+        dev = torch.device(device)
+        self.device = dev
+        self.t = torch.as_tensor(np.ascontiguousarray(t, np.float64)).to(dev)
+        self.y = torch.as_tensor(np.ascontiguousarray(y, np.float64)).to(dev)
+        self.w = None if w is None else torch.as_tensor(np.ascontiguousarray(w, np.float64)).to(dev)
+        nws = (self.plan.workspace_bytes + 255) // 256 * 256
+        self.ws = torch.empty(nws + 256, dtype=torch.uint8, device=dev)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        nf = self.plan.n_freq
+        self.sr = torch.empty(nf, dtype=torch.float64, device=dev)
+        self.best = torch.empty(nf * BEST_DTYPE.itemsize, dtype=torch.uint8, device=dev) if want_best else None
+        self.snr = torch.empty(nf, dtype=torch.float64, device=dev) if want_snr else None
+        self.result = torch.empty(self.plan.n_stars * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        self.plan.upload(self.ws_ptr, self.plan.workspace_bytes, _stream_handle())
+
+    @classmethod
+    def from_batch(cls, batch, params=None, **kw):
+        return cls(batch.t, batch.y, batch.w, batch.offsets, batch.rho, batch.pmin, batch.pmax, params, **kw)
+
+    def run_prepare(self, stream=None):
+        self.plan.prepare(self.ws_ptr, self.t.data_ptr(), self.y.data_ptr(),
+                          None if self.w is None else self.w.data_ptr(), stream=_stream_handle(stream))
+
+    def run_search(self, stream=None, windows=None):
+        h = _stream_handle(stream)
+        self.plan.search(self.ws_ptr, self.sr.data_ptr(), None if self.best is None else self.best.data_ptr(),
+                         None if windows is None else windows.data_ptr(),
+                         0 if windows is None else int(windows.shape[0]), stream=h)
+
+    def run_snr(self, stream=None):
+        h = _stream_handle(stream)
+        self.plan.snr(self.ws_ptr, self.sr.data_ptr(), None if self.best is None else self.best.data_ptr(),
+                      None if self.snr is None else self.snr.data_ptr(), self.result.data_ptr(), stream=h)
+
+    def run(self, stream=None):
+        self.run_prepare(stream)
+        self.run_search(stream)
+        self.run_snr(stream)
+
+    # ---- host copies ----
+    def sr_host(self) -> np.ndarray:
+        return self.sr.cpu().numpy()
+
+    def best_host(self) -> np.ndarray:
+        return self.best.cpu().numpy().view(BEST_DTYPE)
+
+    def snr_host(self) -> np.ndarray:
+        return self.snr.cpu().numpy()
+
+    def results_host(self) -> np.ndarray:
+        return self.result.cpu().numpy().view(RESULT_DTYPE)
+
+    def star_slice(self, s: int) -> slice:
+        fo = self.plan.freq_offsets
+        return slice(int(fo[s]), int(fo[s + 1]))

@@ -1,0 +1,97 @@
+"""Helpers shared by the GPU parity tests: run the HIP path and the oracle on the
+same seeded inputs and compare element by element."""
+import math
+
+import numpy as np
+
+SR_RTOL = 1e-5          # contract: SR within 1e-5 relative of the FP64 oracle
+NEAR_TIE_RTOL = 1e-9    # an (m, j) that differs must be a near-tie of the oracle's power
+
+
+def run_gpu(batch, params=None, want_best=True, want_snr=True):
+    import torch
+    from paper_2302_01293_amd.device import DeviceSearch
+    ds = DeviceSearch.from_batch(batch, params, want_best=want_best, want_snr=want_snr)
+    ds.run()
+    torch.cuda.synchronize()
+    return ds
+
+
+def run_oracle(oracle, batch, stars=None, okw=None, nthreads=0):
+    p = oracle.params(**(okw or {}))
+    return oracle.batch(batch.t, batch.y, batch.w, batch.offsets, batch.rho, batch.pmin, batch.pmax,
+                        p=p, stars=stars, nthreads=nthreads)
+
+
+def window_power(t, y, w, t0, f, nb, m, j):
+    """Oracle-style power of one window from direct sums (for near-tie checks)."""
+    W = w.sum()
+    wt = w / W
+    x = y - np.sum(wt * y)
+    ph = (t - t0) * f
+    ph = ph - np.floor(ph)
+    b = np.minimum(nb - 1, np.floor(ph * nb).astype(np.int64))
+    inw = ((b - j) % nb) < m
+    r, s = wt[inw].sum(), (wt * x)[inw].sum()
+    if not (0 < r < 1):
+        return -1.0
+    return s * s / (r * (1 - r))
+
+
+def compare_star(ds, orc, s_gpu, s_orc, batch_star, label=""):
+    """Compare one star's spectrum and summary; returns stats dict."""
+    sl = ds.star_slice(s_gpu)
+    o0, o1 = int(orc["fofs"][s_orc]), int(orc["fofs"][s_orc + 1])
+    sr_g = ds._sr_host[sl]
+    sr_o = orc["sr"][o0:o1]
+    assert len(sr_g) == len(sr_o), (label, len(sr_g), len(sr_o))
+    denom = np.maximum(np.abs(sr_o), 1e-300)
+    rel = np.abs(sr_g - sr_o) / denom
+    rel[(sr_o == 0) & (sr_g == 0)] = 0.0
+    worst = float(rel.max())
+    assert worst <= SR_RTOL, "%s: SR max rel err %.3e at %d" % (label, worst, int(rel.argmax()))
+    if ds.best is not None:
+        bg = ds._best_host[sl]
+        mm = np.nonzero((bg["m"] != orc["m"][o0:o1]) | (bg["j"] != orc["j"][o0:o1]))[0]
+        t, y, w = batch_star
+        for i in mm[:20]:
+            f, nb = orc["f"][o0 + i], orc["nb"][o0 + i]
+            t0 = t[np.nonzero(w > 0)[0][0]]
+            pg = window_power(t, y, w, t0, f, nb, bg["m"][i], bg["j"][i])
+            po = window_power(t, y, w, t0, f, nb, orc["m"][o0 + i], orc["j"][o0 + i])
+            assert abs(pg - po) <= NEAR_TIE_RTOL * max(abs(po), 1e-300), \
+                "%s: window differs at %d: gpu (%d,%d) %.17g vs oracle (%d,%d) %.17g" % (
+                    label, i, bg["m"][i], bg["j"][i], pg, orc["m"][o0 + i], orc["j"][o0 + i], po)
+        assert len(mm) <= max(2, len(sr_o) // 1000), "%s: %d windows differ" % (label, len(mm))
+        ok = (bg["j"] >= 0) & (orc["j"][o0:o1] >= 0) & (bg["m"] == orc["m"][o0:o1]) & (bg["j"] == orc["j"][o0:o1])
+        if ok.any():
+            np.testing.assert_allclose(bg["r"][ok], orc["r"][o0:o1][ok], rtol=1e-9, atol=1e-15)
+            np.testing.assert_allclose(bg["s"][ok], orc["s"][o0:o1][ok], rtol=1e-5,
+                                       atol=1e-12 * np.abs(orc["s"][o0:o1]).max())
+    # argmax SR and S/N: exact
+    R = ds._res_host[s_gpu]
+    O = orc["results"][s_orc]
+    assert int(R["i_sr"]) == int(O[1]), "%s: argmax SR %d vs %d" % (label, R["i_sr"], O[1])
+    assert int(R["i_snr"]) == int(O[0]), "%s: argmax S/N %d vs %d" % (label, R["i_snr"], O[0])
+    assert R["status"] == int(O[10])
+    assert R["period"] == O[2]
+    if O[10] == 0:
+        assert abs(R["snr"] - O[7]) <= 1e-6 * max(1.0, abs(O[7])), (label, R["snr"], O[7])
+        assert abs(R["sigma"] - O[9]) <= 1e-6 * O[9], (label, R["sigma"], O[9])
+    assert abs(R["trend"] - O[8]) <= 1e-6 * max(abs(O[8]), 1e-12), (label, R["trend"], O[8])
+    if ds.snr is not None and O[10] == 0:
+        sn_g = ds._snr_host[sl]
+        sn_o = orc["snr"][o0:o1]
+        np.testing.assert_allclose(sn_g, sn_o, rtol=1e-5, atol=1e-5 * np.abs(sn_o).max())
+    if ds.best is not None and not math.isnan(O[3]):
+        for q, name in ((3, "t0"), (4, "duration"), (5, "depth")):
+            assert abs(R[name] - O[q]) <= 1e-6 * max(abs(O[q]), 1e-12), (label, name, R[name], O[q])
+    return dict(max_rel_sr=worst)
+
+
+def fetch(ds):
+    ds._sr_host = ds.sr_host()
+    ds._best_host = ds.best_host() if ds.best is not None else None
+    ds._snr_host = ds.snr_host() if ds.snr is not None else None
+    ds._res_host = ds.results_host()
+    return ds

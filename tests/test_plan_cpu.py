@@ -1,0 +1,117 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* the shared library loads and exports every symbol declared in include/mi355bls.h;
+* the plan's grid (f_i, nb_i), period bounds and duration ladder are bit-identical
+  to the oracle's own (independently written) computation;
+* invalid inputs give the documented status codes.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2302_01293_amd import _lib, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "mi355bls.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bls_[a-z_]+)\s*\(", src)))
+
+
+def test_header_matches_binding():
+    assert set(_declared_functions()) == set(_lib.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    L = _lib.lib()
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = _lib.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert L.bls_status_string(code)
+
+
+def _plan_for(batch, **pk):
+    return _lib.Plan(batch.t, batch.y, batch.w, batch.offsets, batch.rho, batch.pmin, batch.pmax,
+                     _lib.default_params(**pk))
+
+
+@pytest.mark.parametrize("which", ["cfg0", "ragged"])
+def test_grid_bit_identical_to_oracle(oracle, which):
+    b = synth.config0() if which == "cfg0" else synth.ragged(10, start=0)
+    plan = _plan_for(b)
+    for s in range(b.n_stars):
+        t, y, w = b.star(s)
+        f_o, nb_o, bd = oracle.grid(t, w, float(b.rho[s]), oracle.params(), float(b.pmin[s]), float(b.pmax[s]))
+        f_p, nb_p = plan.frequencies(s)
+        assert f_p.dtype == np.float64 and len(f_p) == len(f_o)
+        assert np.array_equal(f_p.view(np.uint64), f_o.view(np.uint64))
+        assert np.array_equal(nb_p, nb_o)
+        info = plan.star_info(s)
+        assert info["t0"] == bd.t0 and info["T"] == bd.T
+        assert info["pmin"] == bd.pmin and info["pmax"] == bd.pmax
+        assert info["umin"] == bd.umin and info["A"] == bd.A
+        assert info["sturges"] == oracle.sturges(len(f_o))
+    assert plan.n_freq == sum(int(plan.freq_offsets[s + 1] - plan.freq_offsets[s]) for s in range(b.n_stars))
+
+
+def test_durations_match_oracle(oracle):
+    b = synth.config0()
+    for kw in ({}, {"dlogq": 0.05}, {"noverlap": 4}, {"qmax_fac": 1.5}):
+        plan = _plan_for(b, **kw)
+        assert list(plan.durations()) == list(oracle.durations(oracle.params(**kw)))
+
+
+def test_a_min_three(oracle):
+    b = synth.ragged(3, start=1)
+    plan = _plan_for(b, a_min_rstar=3.0)
+    for s in range(b.n_stars):
+        t, y, w = b.star(s)
+        _, bd = oracle.bounds(t, w, float(b.rho[s]), oracle.params(a_min=3.0))
+        assert plan.star_info(s)["pmin"] == bd.pmin
+
+
+def _raises(code, **mut):
+    b = synth.ragged(2, start=0)
+    t, y, w = b.t.copy(), b.y.copy(), b.w.copy()
+    rho, pmin, pmax = b.rho.copy(), b.pmin.copy(), b.pmax.copy()
+    loc = dict(t=t, y=y, w=w, rho=rho, pmin=pmin, pmax=pmax)
+    for k, fn in mut.items():
+        fn(loc[k])
+    with pytest.raises(_lib.BlsError) as e:
+        _lib.Plan(t, y, w, b.offsets, rho, pmin, pmax)
+    assert e.value.code == code
+
+
+def test_invalid_inputs():
+    _raises(-2, t=lambda a: a.__setitem__(3, np.nan))
+    _raises(-2, y=lambda a: a.__setitem__(5, np.inf))
+    _raises(-2, w=lambda a: a.__setitem__(7, -1.0))
+    _raises(-2, t=lambda a: a.__setitem__(10, a[9] - 1.0))        # not ascending
+    _raises(-2, w=lambda a: a.__setitem__(slice(None), 0.0))      # no weight
+    _raises(-3, pmin=lambda a: a.__setitem__(0, 50.0))           # Pmin >= Pmax
+
+
+def test_zero_weight_points_excluded_from_baseline(oracle):
+    b = synth.ragged(1, start=2)
+    t, y, w = b.star(0)
+    w = w.copy()
+    w[:30] = 0.0
+    w[-10:] = 0.0
+    plan = _lib.Plan(t, y, w, np.array([0, len(t)]), b.rho[:1])
+    _, bd = oracle.bounds(t, w, float(b.rho[0]), oracle.params())
+    info = plan.star_info(0)
+    assert info["t0"] == t[30] == bd.t0 and info["T"] == bd.T
+
+
+def test_limits():
+    lim = _lib.limits()
+    assert lim["nb_max"] >= 4096 and lim["m_max"] >= 12
