@@ -66,7 +66,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg1")
-    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--stars", type=int, default=0, help="use only the first N stars of the workload")
+    ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -80,6 +81,9 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     log("generating workload", args.workload)
     batch, desc = make_workload(args.workload)
+    if args.stars and args.stars < batch.n_stars:
+        batch = batch.subset(np.arange(args.stars))
+        desc += " (first %d stars)" % args.stars
     log("stars", batch.n_stars, "points", batch.n_points)
     ds = DeviceSearch.from_batch(batch)
     nfs = np.diff(ds.plan.freq_offsets)

@@ -208,6 +208,25 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
     const int32_t sturges =
         static_cast<int32_t>(std::floor(1.0 + 3.322 * std::log10(static_cast<double>(d.nf)) + 0.5));
     d.sturges = std::max(1, std::min(sturges, kMaxSturges));
+    // Gap list: points whose time step may advance the phase by a whole fine bin or
+    // more at some grid frequency.  The phase advance of a step dt is dt f nb, and
+    // f nb <= noverlap f^(1/3) / kq + f, largest at the top of the grid; steps below
+    // 0.99 / that bound move at most one bin everywhere.
+    {
+      const double fmax = freq_at(d, d.nf - 1);
+      const double fnb = static_cast<double>(p->noverlap) * std::cbrt(fmax) / d.kq + fmax;
+      const double thr = 0.99 / fnb;
+      d.g_off = static_cast<int64_t>(plan->gaps.size());
+      try {
+        for (int64_t i = 1; i < n; ++i)
+          if (ts[i] - ts[i - 1] >= thr) plan->gaps.push_back(static_cast<int32_t>(i));
+      } catch (...) {
+        return fail(BLS_E_NOMEM);
+      }
+      const int64_t ng = static_cast<int64_t>(plan->gaps.size()) - d.g_off;
+      if (ng > 0x7fffffff) return fail(BLS_E_UNSUPPORTED);
+      d.n_gaps = static_cast<int32_t>(ng);
+    }
     d.f_off = plan->n_freq;
     plan->n_freq += d.nf;
     plan->freq_offsets[s + 1] = plan->n_freq;
@@ -247,6 +266,8 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
   pos = align256(pos + int64_t(sizeof(StarRt)) * n_stars);
   L.items = pos;
   pos = align256(pos + int64_t(sizeof(WorkItem)) * int64_t(plan->items.size()));
+  L.gaps = pos;
+  pos = align256(pos + 4 * std::max<int64_t>(1, static_cast<int64_t>(plan->gaps.size())));
   L.dt = pos;
   pos = align256(pos + 8 * plan->n_points);
   L.cw = pos;

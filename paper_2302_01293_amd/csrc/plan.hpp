@@ -16,10 +16,13 @@
 namespace mi355bls {
 
 // Compiled limits.
-constexpr int kThreads = 1024;        // threads per search / prep / S/N workgroup
-constexpr int kUMax = 12;             // register-resident points per thread
+constexpr int kThreads = 1024;        // threads per prep / S/N workgroup
+constexpr int kSearchThreads = 1024;  // threads per search workgroup (4 waves per SIMD,
+                                      // up to 128 registers per lane)
+constexpr int kUMax = 12;             // register-resident points per search thread
 constexpr int kGBytes = 128 * 1024;   // LDS bytes for the per-frequency accumulators
-constexpr int kNbLimit = kGBytes / 16;  // largest fine-bin count (one frequency per group)
+constexpr int kNbLimit = kGBytes / 32 - 32;  // largest fine-bin count: 32 B of G and D per
+                                              // bin, plus the replicated wrap bins
 constexpr int kFMax = 32;             // most frequencies processed together
 constexpr int kMCap = 32;             // longest duration (in fine bins)
 constexpr int64_t kMaxPoints = int64_t(1) << 30;
@@ -37,10 +40,12 @@ struct StarDesc {
   double kq;        // qmin_fac * krho: q_lo(f) = kq f^(2/3)
   int32_t nb0;      // fine bins at i = 0 (the largest of the star)
   int32_t sturges;  // Sturges bin count of the S/N trend
-  int32_t pad0, pad1;
+  int32_t n_gaps;   // points whose time step can cross more than one fine bin
+  int32_t pad0;
+  int64_t g_off;    // first entry of this star in the gap list
   double T, pmin, pmax, krho;  // descriptive (host queries)
 };
-static_assert(sizeof(StarDesc) == 112, "StarDesc layout");
+static_assert(sizeof(StarDesc) == 120, "StarDesc layout");
 
 // Per-star values written by the preparation kernel.
 struct StarRt {
@@ -66,7 +71,7 @@ struct Consts {
 };
 
 struct Layout {  // byte offsets inside the device workspace
-  int64_t stars, rt, items, dt, cw, cs, rho, total;
+  int64_t stars, rt, items, gaps, dt, cw, cs, rho, total;
 };
 
 }  // namespace mi355bls
@@ -78,6 +83,7 @@ struct bls_plan {
   int64_t n_freq = 0;
   std::vector<mi355bls::StarDesc> stars;
   std::vector<mi355bls::WorkItem> items;
+  std::vector<int32_t> gaps;  // per star (CSR by StarDesc::g_off): point indices n >= 1
   std::vector<int64_t> freq_offsets;
   std::vector<int32_t> durations;
   mi355bls::Consts consts{};

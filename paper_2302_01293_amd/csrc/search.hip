@@ -17,7 +17,9 @@
 //    enters, the telescoping sum gives the exact bin totals
 //        H[b] = G[b+1] - G[b] + [b == bin of the last point] * total.
 //    Whole cycles skipped between two points add the same value to every G and
-//    cancel.  Integer sums are exact, so the result does not depend on order.
+//    cancel; a point that skips bins inside a cycle (data gaps) adds its values
+//    to a range of G, which changes H only at the range ends (the D slots).
+//    Integer sums are exact, so the result does not depend on order.
 //  * Points stay in registers (dt, CW, CS) across all frequencies of a work item;
 //    only boundaries touch LDS (one 64-bit integer atomic pair per boundary).
 //  * The phase frac((t - t0) f) is computed in FP64 with the same IEEE operations
@@ -43,7 +45,7 @@ __device__ __forceinline__ void grid_point(const StarDesc& d, int64_t i, int32_t
 // Fine bin of a point: b = min(nb-1, floor(frac(dt f) nb)).
 __device__ __forceinline__ int32_t fold_bin(double dt, double f, double nbd, int32_t nbm1) {
   const double p = dt * f;
-  const double ph = p - floor(p);
+  const double ph = __builtin_amdgcn_fract(p);  // p - floor(p), exact for finite p >= 0
   const int32_t b = static_cast<int32_t>(ph * nbd);
   return b < nbm1 ? b : nbm1;
 }
@@ -224,10 +226,19 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const StarDesc* __restrict
 
 // ----------------------------------------------------------------------------
 // Fused fold -> boundary accumulation -> H -> duration/phase scan.
-// One workgroup per work item (a frequency range of one star).  LDS holds, per
-// frequency of the current group, nb_cap (W, S) slots: int64 G sums during the
-// fold, then the FP64 bin totals H during the scan.
+// One workgroup per work item (a frequency range of one star).  LDS layout for the
+// F frequencies of the current group, nb_cap bins each (k-major):
+//   [  0, 32K)  GW  int64 G of the weights     -> after conversion HW (FP64 H_W)
+//   [32K, 64K)  GS  int64 G of the residuals   -> after conversion HS (FP64 H_S)
+//   [64K, 96K)  DW  int64 range-add ends at data gaps (weights)
+//   [96K,128K)  DS  int64 range-add ends at data gaps (residuals)
+// Separate 8-byte arrays keep the boundary atomics of a wave on distinct banks,
+// and GS sits at a fixed offset from GW (one address per atomic pair).
 // ----------------------------------------------------------------------------
+constexpr int kArrBytes = kGBytes / 4;   // 32 KB per array
+constexpr int kUGroup = 4;               // points whose bins are computed together
+constexpr int kArrElems = kArrBytes / 8; // F * nb_cap <= 4096
+
 struct SearchArgs {
   const StarDesc* stars;
   const StarRt* rt;
@@ -235,32 +246,56 @@ struct SearchArgs {
   const double* dt;
   const int64_t* cw;
   const int64_t* cs;
+  const int32_t* gaps;     // per-star lists of points whose step can skip bins
   const int64_t* windows;  // optional (star, i0, i1) triples replacing items
   double* sr;
   bls_best* best;
   Consts c;
 };
 
+// Best window of a lane or wave: power s^2 / d kept as the pair (s^2, d) so that
+// comparisons need no division; mj = (m << 20) | j orders ties lexicographically.
+// The empty state is (-1, 1, ~0): every valid window beats it.
 struct ScanBest {
-  double p2;
-  int32_t m, j;
+  double ss, d;
+  uint32_t mj;
+  uint32_t pad;
 };
 
-__device__ __forceinline__ bool better(double p2, int32_t m, int32_t j, double q2, int32_t qm, int32_t qj) {
-  return p2 > q2 || (p2 == q2 && (m < qm || (m == qm && j < qj)));
+__device__ __forceinline__ bool better(double ssa, double da, uint32_t mja, double ssb, double db, uint32_t mjb) {
+  const double x = ssa * db, y = ssb * da;
+  return x > y || (x == y && mja < mjb);
 }
+
+constexpr int kScanUnroll = 16;  // durations up to this length run fully unrolled
 
 constexpr double kW62 = 2.168404344971008868e-19;  // 2^-62
 
-__global__ void __launch_bounds__(kThreads) k_search(SearchArgs a) {
+// Fine bin without the clamp: fract() returns at most 1 - 2^-53, and for any
+// integer nb >= 1, (1 - 2^-53) nb rounds to a value below nb, so the truncation
+// is at most nb - 1 (the same bin as min(nb-1, floor(frac nb))).
+__device__ __forceinline__ int32_t fold_bin_nc(double dt, double f, double nbd) {
+  return static_cast<int32_t>(__builtin_amdgcn_fract(dt * f) * nbd);
+}
+
+__device__ __forceinline__ void lds_add64(unsigned char* base, uint32_t byte_off, long long v) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(base + byte_off), static_cast<unsigned long long>(v));
+}
+
+__global__ void __launch_bounds__(kSearchThreads) k_search(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  unsigned long long* G = reinterpret_cast<unsigned long long*>(smem);
-  double* H = reinterpret_cast<double*>(smem);
+  long long* GW = reinterpret_cast<long long*>(smem);
+  long long* GS = reinterpret_cast<long long*>(smem + kArrBytes);
+  long long* DW = reinterpret_cast<long long*>(smem + 2 * kArrBytes);
+  long long* DS = reinterpret_cast<long long*>(smem + 3 * kArrBytes);
+  double* HW = reinterpret_cast<double*>(smem);
+  double* HS = reinterpret_cast<double*>(smem + kArrBytes);
   double* s_f = reinterpret_cast<double*>(smem + kGBytes);
   int32_t* s_nb = reinterpret_cast<int32_t*>(s_f + kFMax);
   int32_t* s_blast = s_nb + kFMax;
-  long long* s_g0 = reinterpret_cast<long long*>(s_blast + kFMax);  // [kFMax][2]
-  ScanBest* s_res = reinterpret_cast<ScanBest*>(s_g0 + 2 * kFMax);   // [kFMax][16]
+  long long* s_g0w = reinterpret_cast<long long*>(s_blast + kFMax);
+  long long* s_g0s = s_g0w + kFMax;
+  ScanBest* s_res = reinterpret_cast<ScanBest*>(s_g0s + kFMax);  // [kFMax][16]
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -288,7 +323,10 @@ __global__ void __launch_bounds__(kThreads) k_search(SearchArgs a) {
   int32_t nb_cap;
   grid_point(d, it.i0, noverlap, f_first, nb_cap);
   if (nb_cap > kNbLimit || nb_cap < 1) return;  // rejected by the plan
-  const int F_act = min(kFMax, (kGBytes / 16) / nb_cap);
+  // Slot stride: nb_cap bins plus room to replicate the first bins after the
+  // last, so windows that wrap past bin nb-1 read contiguously.
+  const int stride = nb_cap + kMCap;
+  const int F_act = min(kFMax, kArrElems / stride);
 
   // Points: thread t owns a contiguous run of `run` points per chunk.
   const int T = blockDim.x;
@@ -297,23 +335,23 @@ __global__ void __launch_bounds__(kThreads) k_search(SearchArgs a) {
   const int nchunks = static_cast<int>((n + chunk_pts - 1) / chunk_pts);
   double dtr[kUMax];
   long long cwr[kUMax], csr[kUMax];
-  double dtp = 0.0;
-  int len = 0;
-  bool has_prev = false;
+  double dtp = 0.0;  // time of the point before the run (the run's first point if none)
+  bool active = false;
   auto load_chunk = [&](int c) {
     const int64_t s = static_cast<int64_t>(c) * chunk_pts + static_cast<int64_t>(tid) * run;
     const int64_t rem = n - s;
-    len = rem <= 0 ? 0 : static_cast<int>(min<int64_t>(run, rem));
-    has_prev = (s > 0) && (len > 0);
-    dtp = has_prev ? dt[s - 1] : 0.0;
+    const int len = rem <= 0 ? 0 : static_cast<int>(min<int64_t>(run, rem));
+    active = len > 0;
+    if (!active) return;
+    // Points past the end repeat the last one: same bin, so no boundary.
 #pragma unroll
     for (int u = 0; u < kUMax; ++u) {
-      if (u < len) {
-        dtr[u] = dt[s + u];
-        cwr[u] = cw[s + u];
-        csr[u] = cs[s + u];
-      }
+      const int64_t q = s + (u < len ? u : len - 1);
+      dtr[u] = dt[q];
+      cwr[u] = cw[q];
+      csr[u] = cs[q];
     }
+    dtp = s > 0 ? dt[s - 1] : dtr[0];
   };
   if (nchunks == 1) load_chunk(0);
   const double dt_last = dt[n - 1];
@@ -327,147 +365,223 @@ __global__ void __launch_bounds__(kThreads) k_search(SearchArgs a) {
       grid_point(d, g0 + tid, noverlap, f, nb);
       s_f[tid] = f;
       s_nb[tid] = nb;
-      s_blast[tid] = fold_bin(dt_last, f, static_cast<double>(nb), nb - 1);
+      s_blast[tid] = fold_bin_nc(dt_last, f, static_cast<double>(nb));
     }
-    for (int idx = tid; idx < F * nb_cap * 2; idx += T) G[idx] = 0ull;
+    for (int idx = tid; idx < F * stride; idx += T) {
+      GW[idx] = 0;
+      GS[idx] = 0;
+      DW[idx] = 0;
+      DS[idx] = 0;
+    }
     __syncthreads();
 
-    // ---- fold: boundaries add the prefix values into G ----
+    // ---- fold: a point whose bin differs from its predecessor's is a boundary
+    // and adds its prefix values into G of its bin.  Two frequencies per pass give
+    // the scheduler two independent chains per point.
     for (int c = 0; c < nchunks; ++c) {
       if (nchunks > 1) load_chunk(c);
-      for (int k = 0; k < F; ++k) {
+      if (!active) continue;
+      for (int k0 = 0; k0 < F; k0 += 2) {
+        const int k1 = min(k0 + 1, F - 1);
+        const bool two = k1 != k0;
+        const double fa = s_f[k0], fb = s_f[k1];
+        const double na = static_cast<double>(s_nb[k0]), nbv = static_cast<double>(s_nb[k1]);
+        unsigned char* const ga = smem + static_cast<uint32_t>(k0 * stride) * 8u;
+        unsigned char* const gb = smem + static_cast<uint32_t>(k1 * stride) * 8u;
+        int32_t pa = fold_bin_nc(dtp, fa, na);
+        int32_t pb = fold_bin_nc(dtp, fb, nbv);
+#pragma unroll
+        for (int u0 = 0; u0 < kUMax; u0 += kUGroup) {
+          // Bins of a group of points for both frequencies first: independent FP64
+          // chains the scheduler can overlap (the empty asm keeps the compiler from
+          // sinking them into the branches below).
+          // Stage by stage across the group, so that the chains overlap.
+          double xa[kUGroup], xb[kUGroup];
+          int32_t ba[kUGroup], bb[kUGroup];
+#pragma unroll
+          for (int v = 0; v < kUGroup; ++v) {
+            xa[v] = dtr[u0 + v] * fa;
+            xb[v] = dtr[u0 + v] * fb;
+          }
+#pragma unroll
+          for (int v = 0; v < kUGroup; ++v) asm volatile("" : "+v"(xa[v]), "+v"(xb[v]));
+#pragma unroll
+          for (int v = 0; v < kUGroup; ++v) {
+            xa[v] = __builtin_amdgcn_fract(xa[v]);
+            xb[v] = __builtin_amdgcn_fract(xb[v]);
+          }
+#pragma unroll
+          for (int v = 0; v < kUGroup; ++v) asm volatile("" : "+v"(xa[v]), "+v"(xb[v]));
+#pragma unroll
+          for (int v = 0; v < kUGroup; ++v) {
+            xa[v] = xa[v] * na;
+            xb[v] = xb[v] * nbv;
+          }
+#pragma unroll
+          for (int v = 0; v < kUGroup; ++v) asm volatile("" : "+v"(xa[v]), "+v"(xb[v]));
+#pragma unroll
+          for (int v = 0; v < kUGroup; ++v) {
+            ba[v] = static_cast<int32_t>(xa[v]);
+            bb[v] = static_cast<int32_t>(xb[v]);
+          }
+#pragma unroll
+          for (int v = 0; v < kUGroup; ++v) asm volatile("" ::"v"(ba[v]), "v"(bb[v]));
+#pragma unroll
+          for (int v = 0; v < kUGroup; ++v) {
+            const int u = u0 + v;
+            if (ba[v] != pa) {
+              unsigned char* o = ga + 8u * static_cast<uint32_t>(ba[v]);
+              lds_add64(o, 0, cwr[u]);
+              lds_add64(o, kArrBytes, csr[u]);
+            }
+            if (two && bb[v] != pb) {
+              unsigned char* o = gb + 8u * static_cast<uint32_t>(bb[v]);
+              lds_add64(o, 0, cwr[u]);
+              lds_add64(o, kArrBytes, csr[u]);
+            }
+            pa = ba[v];
+            pb = bb[v];
+          }
+        }
+      }
+    }
+    // A point whose time step crosses more than one fine bin (a data gap) belongs
+    // to every bin in (bp, b]: G[b] has its prefix values from the fold; adding them
+    // to the skipped bins (bp, b-1] changes H = G[b+1] - G[b] only at the two ends
+    // of that range, recorded in D: D[bp] += E, D[b-1] -= E.  Only points in the
+    // star's gap list can do this (their step is large compared with the bin width
+    // at the top of the grid).
+    if (d.n_gaps > 0) {
+      const int32_t* gl = a.gaps + d.g_off;
+      const int total_g = F * d.n_gaps;
+      for (int idx = tid; idx < total_g; idx += T) {
+        const int k = idx / d.n_gaps;
+        const int32_t q = gl[idx - k * d.n_gaps];
         const double f = s_f[k];
         const int32_t nb = s_nb[k];
         const double nbd = static_cast<double>(nb);
-        const int32_t nbm1 = nb - 1;
-        unsigned long long* Gk = G + static_cast<size_t>(k) * nb_cap * 2;
-        int32_t bprev = has_prev ? fold_bin(dtp, f, nbd, nbm1) : -1;
-#pragma unroll
-        for (int u = 0; u < kUMax; ++u) {
-          if (u < len) {
-            const int32_t b = fold_bin(dtr[u], f, nbd, nbm1);
-            if (b != bprev) {
-              if (bprev >= 0) {
-                const unsigned long long ew = static_cast<unsigned long long>(cwr[u]);
-                const unsigned long long es = static_cast<unsigned long long>(csr[u]);
-                atomicAdd(&Gk[2 * b], ew);
-                atomicAdd(&Gk[2 * b + 1], es);
-                int32_t steps = b - bprev;
-                if (steps < 0) steps += nb;
-                int32_t beta = b;
-                for (int32_t q = 1; q < steps; ++q) {
-                  beta = beta == 0 ? nbm1 : beta - 1;
-                  atomicAdd(&Gk[2 * beta], ew);
-                  atomicAdd(&Gk[2 * beta + 1], es);
-                }
-              }
-              bprev = b;
-            }
-          }
+        const int32_t bq = fold_bin_nc(dt[q - 1], f, nbd);
+        const int32_t bu = fold_bin_nc(dt[q], f, nbd);
+        int32_t steps = bu - bq;
+        if (steps < 0) steps += nb;
+        if (steps > 1) {
+          const int32_t bm1 = bu == 0 ? nb - 1 : bu - 1;
+          const uint32_t kb = static_cast<uint32_t>(k * stride);
+          const long long ew = cw[q], es = cs[q];
+          atomicAdd(reinterpret_cast<unsigned long long*>(&DW[kb + bq]), static_cast<unsigned long long>(ew));
+          atomicAdd(reinterpret_cast<unsigned long long*>(&DS[kb + bq]), static_cast<unsigned long long>(es));
+          atomicAdd(reinterpret_cast<unsigned long long*>(&DW[kb + bm1]), 0ull - static_cast<unsigned long long>(ew));
+          atomicAdd(reinterpret_cast<unsigned long long*>(&DS[kb + bm1]), 0ull - static_cast<unsigned long long>(es));
         }
       }
     }
     __syncthreads();
 
-    // ---- G -> H (in place, chunked), with the wrap slot saved first ----
+    // ---- G -> H in place, in chunks of T bins (all reads of a chunk precede its
+    // writes; the wrap value G[k][0] is saved first) ----
     if (tid < F) {
-      s_g0[2 * tid] = static_cast<long long>(G[static_cast<size_t>(tid) * nb_cap * 2]);
-      s_g0[2 * tid + 1] = static_cast<long long>(G[static_cast<size_t>(tid) * nb_cap * 2 + 1]);
+      s_g0w[tid] = GW[tid * stride];
+      s_g0s[tid] = GS[tid * stride];
     }
     __syncthreads();
-    const int total = F * nb_cap;
+    const int total = F * stride;
     for (int base = 0; base < total; base += T) {
       const int idx = base + tid;
       bool act = false;
       double hw = 0.0, hs = 0.0;
-      int k = 0, b = 0;
       if (idx < total) {
-        k = idx / nb_cap;
-        b = idx - k * nb_cap;
+        const int k = idx / stride;
+        const int b = idx - k * stride;
         const int32_t nb = s_nb[k];
         if (b < nb) {
           act = true;
-          const unsigned long long* Gk = G + static_cast<size_t>(k) * nb_cap * 2;
-          const long long w0 = static_cast<long long>(Gk[2 * b]);
-          const long long s0 = static_cast<long long>(Gk[2 * b + 1]);
-          long long w1, s1;
-          if (b + 1 < nb) {
-            w1 = static_cast<long long>(Gk[2 * b + 2]);
-            s1 = static_cast<long long>(Gk[2 * b + 3]);
-          } else {
-            w1 = s_g0[2 * k];
-            s1 = s_g0[2 * k + 1];
-          }
-          long long dw = static_cast<long long>(static_cast<unsigned long long>(w1) - static_cast<unsigned long long>(w0));
-          long long ds = static_cast<long long>(static_cast<unsigned long long>(s1) - static_cast<unsigned long long>(s0));
+          const unsigned long long w0 = static_cast<unsigned long long>(GW[idx] - DW[idx]);
+          const unsigned long long s0 = static_cast<unsigned long long>(GS[idx] - DS[idx]);
+          const unsigned long long w1 = static_cast<unsigned long long>(b + 1 < nb ? GW[idx + 1] : s_g0w[k]);
+          const unsigned long long s1 = static_cast<unsigned long long>(b + 1 < nb ? GS[idx + 1] : s_g0s[k]);
+          unsigned long long dw = w1 - w0, ds = s1 - s0;
           if (b == s_blast[k]) {
-            dw = static_cast<long long>(static_cast<unsigned long long>(dw) + static_cast<unsigned long long>(rt.cw_total));
-            ds = static_cast<long long>(static_cast<unsigned long long>(ds) + static_cast<unsigned long long>(rt.cs_total));
+            dw += static_cast<unsigned long long>(rt.cw_total);
+            ds += static_cast<unsigned long long>(rt.cs_total);
           }
-          hw = static_cast<double>(dw) * kW62;
-          hs = static_cast<double>(ds) * rt.s_scale;
+          hw = static_cast<double>(static_cast<long long>(dw)) * kW62;
+          hs = static_cast<double>(static_cast<long long>(ds)) * rt.s_scale;
         }
       }
       __syncthreads();
       if (act) {
-        double* Hk = H + static_cast<size_t>(k) * nb_cap * 2;
-        Hk[2 * b] = hw;
-        Hk[2 * b + 1] = hs;
+        HW[idx] = hw;
+        HS[idx] = hs;
       }
       __syncthreads();
     }
 
-    // ---- scan: every start bin j, durations m of the ladder ----
-    const int wpk = F <= waves ? waves / F : 1;   // waves per frequency
-    const int kstep = waves / wpk;
+    // Replicate the first bins after the last one (windows wrap past nb - 1).
     const int m_max = a.c.m_max;
+    for (int idx = tid; idx < F * kMCap; idx += T) {
+      const int k = idx / kMCap;
+      const int i = idx - k * kMCap;
+      const int32_t nb = s_nb[k];
+      if (i < min(m_max, nb - 1)) {
+        HW[k * stride + nb + i] = HW[k * stride + i];
+        HS[k * stride + nb + i] = HS[k * stride + i];
+      }
+    }
+    __syncthreads();
+
+    // ---- scan: every start bin j, durations m of the ladder.  Branch-free running
+    // maximum of s^2 / (r (1 - r)) compared as cross products. ----
+    const int wpk = F <= waves ? waves / F : 1;  // waves per frequency
+    const int kstep = waves / wpk;
     const uint32_t m_mask = a.c.m_mask;
     const bool dip = a.c.dip_only != 0;
     for (int k = wave / wpk; k < F; k += kstep) {
       const int sub = wave - (wave / wpk) * wpk;
       const int32_t nb = s_nb[k];
-      const double* Hk = H + static_cast<size_t>(k) * nb_cap * 2;
-      double bp = -1.0, tp = -1.0;
-      int32_t bm = 0, bj = -1;
+      const double* hwk = HW + k * stride;
+      const double* hsk = HS + k * stride;
+      double bss = -1.0, bd = 1.0;
+      uint32_t bmj = ~0u;
       const int mlim = min(m_max, nb - 1);
+      auto window = [&](int m, int j, double r, double s) {
+        const double dd = fma(-r, r, r);  // r (1 - r) > 0  <=>  0 < r < 1
+        const double ss = s * s;
+        const uint32_t mj = (static_cast<uint32_t>(m) << 20) | static_cast<uint32_t>(j);
+        const bool ok = dd > 0.0 && (!dip || s < 0.0);
+        if (ok && better(ss, dd, mj, bss, bd, bmj)) {
+          bss = ss;
+          bd = dd;
+          bmj = mj;
+        }
+      };
       for (int j = sub * 64 + lane; j < nb; j += wpk * 64) {
         double r = 0.0, s = 0.0;
-        int idx = j;
-        for (int m = 1; m <= mlim; ++m) {
-          const double2 h = *reinterpret_cast<const double2*>(Hk + 2 * idx);
-          r += h.x;
-          s += h.y;
-          idx = idx + 1 == nb ? 0 : idx + 1;
-          if (m_mask & (1u << (m - 1))) {
-            const double da = fma(-r, r, r);
-            const double ss = s * s;
-            if (fma(-tp, da, ss) > 0.0) {
-              if (r > 0.0 && r < 1.0 && (!dip || s < 0.0)) {
-                const double p2 = (s * s) / (r * (1.0 - r));
-                if (better(p2, m, j, bp, bm, bj)) {
-                  bp = p2;
-                  bm = m;
-                  bj = j;
-                  tp = bp > 0.0 ? bp * (1.0 - 0x1.0p-40) : -1.0;
-                }
-              }
-            }
+#pragma unroll
+        for (int m = 1; m <= kScanUnroll; ++m) {
+          if (m <= mlim) {
+            r += hwk[j + m - 1];
+            s += hsk[j + m - 1];
+            if (m_mask & (1u << (m - 1))) window(m, j, r, s);
           }
         }
-      }
-      // wave reduction of (p2, m, j)
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double q2 = __shfl_xor(bp, o, 64);
-        const int32_t qm = __shfl_xor(bm, o, 64);
-        const int32_t qj = __shfl_xor(bj, o, 64);
-        if (better(q2, qm, qj, bp, bm, bj)) {
-          bp = q2;
-          bm = qm;
-          bj = qj;
+        for (int m = kScanUnroll + 1; m <= mlim; ++m) {
+          r += hwk[j + m - 1];
+          s += hsk[j + m - 1];
+          if (m_mask & (1u << (m - 1))) window(m, j, r, s);
         }
       }
-      if (lane == 0) s_res[k * 16 + sub] = ScanBest{bp, bm, bj};
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double qss = __shfl_xor(bss, o, 64);
+        const double qd = __shfl_xor(bd, o, 64);
+        const uint32_t qmj = __shfl_xor(bmj, o, 64);
+        if (better(qss, qd, qmj, bss, bd, bmj)) {
+          bss = qss;
+          bd = qd;
+          bmj = qmj;
+        }
+      }
+      if (lane == 0) s_res[k * 16 + sub] = ScanBest{bss, bd, bmj, 0u};
     }
     __syncthreads();
     if (tid < F) {
@@ -475,32 +589,31 @@ __global__ void __launch_bounds__(kThreads) k_search(SearchArgs a) {
       ScanBest bsel = s_res[k * 16];
       for (int q = 1; q < wpk; ++q) {
         const ScanBest o = s_res[k * 16 + q];
-        if (better(o.p2, o.m, o.j, bsel.p2, bsel.m, bsel.j)) bsel = o;
+        if (better(o.ss, o.d, o.mj, bsel.ss, bsel.d, bsel.mj)) bsel = o;
       }
       const int64_t fi = d.f_off + g0 + k;
       bls_best bb;
-      if (bsel.p2 >= 0.0 && bsel.j >= 0) {
-        const int32_t nb = s_nb[k];
-        const double* Hk = H + static_cast<size_t>(k) * nb_cap * 2;
+      bb.m = 0;
+      bb.j = -1;
+      bb.r = 0.0;
+      bb.s = 0.0;
+      double sr = 0.0;
+      if (bsel.mj != ~0u) {
+        const int m = static_cast<int>(bsel.mj >> 20), j = static_cast<int>(bsel.mj & 0xFFFFFu);
+        const double* hwk = HW + k * stride;
+        const double* hsk = HS + k * stride;
         double r = 0.0, s = 0.0;
-        int idx = bsel.j;
-        for (int m = 1; m <= bsel.m; ++m) {
-          r += Hk[2 * idx];
-          s += Hk[2 * idx + 1];
-          idx = idx + 1 == nb ? 0 : idx + 1;
+        for (int u = 0; u < m; ++u) {
+          r += hwk[j + u];
+          s += hsk[j + u];
         }
-        a.sr[fi] = sqrt(bsel.p2);
-        bb.m = bsel.m;
-        bb.j = bsel.j;
+        sr = sqrt((s * s) / (r * (1.0 - r)));
+        bb.m = m;
+        bb.j = j;
         bb.r = r;
         bb.s = s;
-      } else {
-        a.sr[fi] = 0.0;
-        bb.m = 0;
-        bb.j = -1;
-        bb.r = 0.0;
-        bb.s = 0.0;
       }
+      a.sr[fi] = sr;
       if (a.best) a.best[fi] = bb;
     }
     __syncthreads();
@@ -529,6 +642,10 @@ extern "C" bls_status bls_plan_upload(bls_plan* plan, void* ws, int64_t bytes, b
     return BLS_E_HIP;
   if (!plan->items.empty() &&
       hipMemcpyAsync(base + plan->layout.items, plan->items.data(), sizeof(WorkItem) * plan->items.size(),
+                     hipMemcpyHostToDevice, st) != hipSuccess)
+    return BLS_E_HIP;
+  if (!plan->gaps.empty() &&
+      hipMemcpyAsync(base + plan->layout.gaps, plan->gaps.data(), sizeof(int32_t) * plan->gaps.size(),
                      hipMemcpyHostToDevice, st) != hipSuccess)
     return BLS_E_HIP;
   plan->uploaded_to = ws;
@@ -566,14 +683,16 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
   a.dt = reinterpret_cast<const double*>(base + L.dt);
   a.cw = reinterpret_cast<const int64_t*>(base + L.cw);
   a.cs = reinterpret_cast<const int64_t*>(base + L.cs);
+  a.gaps = reinterpret_cast<const int32_t*>(base + L.gaps);
   a.windows = d_windows;
   a.sr = d_sr;
   a.best = d_best;
   a.c = plan->consts;
   const int64_t n_items = d_windows ? n_windows : static_cast<int64_t>(plan->items.size());
   if (n_items == 0) return BLS_OK;
-  const size_t lds = kGBytes + kFMax * (8 + 4 + 4 + 16) + kFMax * 16 * sizeof(ScanBest);
-  hipLaunchKernelGGL(k_search, dim3(static_cast<unsigned>(n_items)), dim3(kThreads), lds, st, a);
+  const size_t lds = kGBytes + kFMax * (8 + 4 + 4 + 8 + 8) + kFMax * 16 * sizeof(ScanBest);
+  static_assert(kGBytes + kFMax * 32 + kFMax * 16 * sizeof(ScanBest) <= 160 * 1024, "LDS budget");
+  hipLaunchKernelGGL(k_search, dim3(static_cast<unsigned>(n_items)), dim3(kSearchThreads), lds, st, a);
   if (hipGetLastError() != hipSuccess) return BLS_E_HIP;
   return BLS_OK;
 }
