@@ -282,6 +282,94 @@ __device__ __forceinline__ void lds_add64(unsigned char* base, uint32_t byte_off
   atomicAdd(reinterpret_cast<unsigned long long*>(base + byte_off), static_cast<unsigned long long>(v));
 }
 
+// One pass of the fold over the wave's block for frequencies k0 and, when TWO,
+// k0 + 1: a point whose bin differs from its predecessor's is a boundary and adds
+// its prefix values into G of its bin.
+template <bool TWO>
+__device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k0, const double* s_f,
+                                          const int32_t* s_nb, const double (&dtr)[kUMax],
+                                          const long long (&cwr)[kUMax], const long long (&csr)[kUMax],
+                                          double dt_before, int run, int lane) {
+  const int k1 = TWO ? k0 + 1 : k0;
+  const double fa = s_f[k0], fb = s_f[k1];
+  const double na = static_cast<double>(s_nb[k0]), nbv = static_cast<double>(s_nb[k1]);
+  const uint32_t ga = static_cast<uint32_t>(k0 * stride) * 8u;
+  const uint32_t gb = static_cast<uint32_t>(k1 * stride) * 8u;
+  // Bin of the point before the block: the predecessor of lane 0 at step 0.
+  int32_t carry_a = fold_bin_nc(dt_before, fa, na);
+  int32_t carry_b = TWO ? fold_bin_nc(dt_before, fb, nbv) : 0;
+#pragma unroll
+  for (int u0 = 0; u0 < kUMax; u0 += kUGroup) {
+    if (u0 >= run) break;
+    // Bins of a group of steps for both frequencies, stage by stage so the
+    // independent FP64 chains overlap (the empty asm statements pin the order;
+    // without them the compiler sinks each chain into its branch).
+    double xa[kUGroup], xb[kUGroup];
+    int32_t ba[kUGroup], bb[kUGroup];
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) {
+      xa[v] = dtr[u0 + v] * fa;
+      if (TWO) xb[v] = dtr[u0 + v] * fb;
+    }
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) {
+      asm volatile("" : "+v"(xa[v]));
+      if (TWO) asm volatile("" : "+v"(xb[v]));
+    }
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) {
+      xa[v] = __builtin_amdgcn_fract(xa[v]);
+      if (TWO) xb[v] = __builtin_amdgcn_fract(xb[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) {
+      asm volatile("" : "+v"(xa[v]));
+      if (TWO) asm volatile("" : "+v"(xb[v]));
+    }
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) {
+      xa[v] = xa[v] * na;
+      if (TWO) xb[v] = xb[v] * nbv;
+    }
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) {
+      asm volatile("" : "+v"(xa[v]));
+      if (TWO) asm volatile("" : "+v"(xb[v]));
+    }
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) {
+      ba[v] = static_cast<int32_t>(xa[v]);
+      bb[v] = TWO ? static_cast<int32_t>(xb[v]) : 0;
+    }
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) asm volatile("" ::"v"(ba[v]), "v"(bb[v]));
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) {
+      const int u = u0 + v;
+      // Predecessor bins: lane l-1 of this step (DPP wave shift right by one);
+      // lane 0 takes lane 63 of the previous step.
+      const int32_t la = v == 0 ? carry_a : __builtin_amdgcn_readlane(ba[v - 1], 63);
+      const int32_t pa = __builtin_amdgcn_update_dpp(la, ba[v], 0x138, 0xf, 0xf, false);
+      if (ba[v] != pa) {
+        const uint32_t o = ga + 8u * static_cast<uint32_t>(ba[v]);
+        lds_add64(smem, o, cwr[u]);
+        lds_add64(smem, o + kArrBytes, csr[u]);
+      }
+      if (TWO) {
+        const int32_t lb = v == 0 ? carry_b : __builtin_amdgcn_readlane(bb[v - 1], 63);
+        const int32_t pb = __builtin_amdgcn_update_dpp(lb, bb[v], 0x138, 0xf, 0xf, false);
+        if (bb[v] != pb) {
+          const uint32_t o = gb + 8u * static_cast<uint32_t>(bb[v]);
+          lds_add64(smem, o, cwr[u]);
+          lds_add64(smem, o + kArrBytes, csr[u]);
+        }
+      }
+    }
+    carry_a = __builtin_amdgcn_readlane(ba[kUGroup - 1], 63);
+    if (TWO) carry_b = __builtin_amdgcn_readlane(bb[kUGroup - 1], 63);
+  }
+}
+
 __global__ void __launch_bounds__(kSearchThreads) k_search(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   long long* GW = reinterpret_cast<long long*>(smem);
@@ -328,30 +416,32 @@ __global__ void __launch_bounds__(kSearchThreads) k_search(SearchArgs a) {
   const int stride = nb_cap + kMCap;
   const int F_act = min(kFMax, kArrElems / stride);
 
-  // Points: thread t owns a contiguous run of `run` points per chunk.
+  // Points: wave w owns a contiguous block of 64 * run points per chunk; lane l holds
+  // points block + 64 u + l, so a point's predecessor is in the previous lane of the
+  // same step (lane 0: lane 63 of the previous step).  Loads are coalesced and the
+  // boundaries of one step fall on consecutive bins.
   const int T = blockDim.x;
   const int run = static_cast<int>(min<int64_t>(kUMax, (n + T - 1) / T));
   const int64_t chunk_pts = static_cast<int64_t>(run) * T;
   const int nchunks = static_cast<int>((n + chunk_pts - 1) / chunk_pts);
   double dtr[kUMax];
   long long cwr[kUMax], csr[kUMax];
-  double dtp = 0.0;  // time of the point before the run (the run's first point if none)
+  double dt_before = 0.0;  // time of the point before the wave's block (its first if none)
   bool active = false;
   auto load_chunk = [&](int c) {
-    const int64_t s = static_cast<int64_t>(c) * chunk_pts + static_cast<int64_t>(tid) * run;
-    const int64_t rem = n - s;
-    const int len = rem <= 0 ? 0 : static_cast<int>(min<int64_t>(run, rem));
-    active = len > 0;
+    const int64_t wbase = static_cast<int64_t>(c) * chunk_pts + static_cast<int64_t>(wave) * 64 * run;
+    active = wbase < n;
     if (!active) return;
-    // Points past the end repeat the last one: same bin, so no boundary.
+    const int64_t wend = min<int64_t>(n, wbase + static_cast<int64_t>(64) * run);
+    // Points past the block's end repeat its last point: same bin, no boundary.
 #pragma unroll
     for (int u = 0; u < kUMax; ++u) {
-      const int64_t q = s + (u < len ? u : len - 1);
+      const int64_t q = min<int64_t>(wbase + u * 64 + lane, wend - 1);
       dtr[u] = dt[q];
       cwr[u] = cw[q];
       csr[u] = cs[q];
     }
-    dtp = s > 0 ? dt[s - 1] : dtr[0];
+    dt_before = dt[wbase > 0 ? wbase - 1 : 0];
   };
   if (nchunks == 1) load_chunk(0);
   const double dt_last = dt[n - 1];
@@ -382,67 +472,10 @@ __global__ void __launch_bounds__(kSearchThreads) k_search(SearchArgs a) {
       if (nchunks > 1) load_chunk(c);
       if (!active) continue;
       for (int k0 = 0; k0 < F; k0 += 2) {
-        const int k1 = min(k0 + 1, F - 1);
-        const bool two = k1 != k0;
-        const double fa = s_f[k0], fb = s_f[k1];
-        const double na = static_cast<double>(s_nb[k0]), nbv = static_cast<double>(s_nb[k1]);
-        unsigned char* const ga = smem + static_cast<uint32_t>(k0 * stride) * 8u;
-        unsigned char* const gb = smem + static_cast<uint32_t>(k1 * stride) * 8u;
-        int32_t pa = fold_bin_nc(dtp, fa, na);
-        int32_t pb = fold_bin_nc(dtp, fb, nbv);
-#pragma unroll
-        for (int u0 = 0; u0 < kUMax; u0 += kUGroup) {
-          // Bins of a group of points for both frequencies first: independent FP64
-          // chains the scheduler can overlap (the empty asm keeps the compiler from
-          // sinking them into the branches below).
-          // Stage by stage across the group, so that the chains overlap.
-          double xa[kUGroup], xb[kUGroup];
-          int32_t ba[kUGroup], bb[kUGroup];
-#pragma unroll
-          for (int v = 0; v < kUGroup; ++v) {
-            xa[v] = dtr[u0 + v] * fa;
-            xb[v] = dtr[u0 + v] * fb;
-          }
-#pragma unroll
-          for (int v = 0; v < kUGroup; ++v) asm volatile("" : "+v"(xa[v]), "+v"(xb[v]));
-#pragma unroll
-          for (int v = 0; v < kUGroup; ++v) {
-            xa[v] = __builtin_amdgcn_fract(xa[v]);
-            xb[v] = __builtin_amdgcn_fract(xb[v]);
-          }
-#pragma unroll
-          for (int v = 0; v < kUGroup; ++v) asm volatile("" : "+v"(xa[v]), "+v"(xb[v]));
-#pragma unroll
-          for (int v = 0; v < kUGroup; ++v) {
-            xa[v] = xa[v] * na;
-            xb[v] = xb[v] * nbv;
-          }
-#pragma unroll
-          for (int v = 0; v < kUGroup; ++v) asm volatile("" : "+v"(xa[v]), "+v"(xb[v]));
-#pragma unroll
-          for (int v = 0; v < kUGroup; ++v) {
-            ba[v] = static_cast<int32_t>(xa[v]);
-            bb[v] = static_cast<int32_t>(xb[v]);
-          }
-#pragma unroll
-          for (int v = 0; v < kUGroup; ++v) asm volatile("" ::"v"(ba[v]), "v"(bb[v]));
-#pragma unroll
-          for (int v = 0; v < kUGroup; ++v) {
-            const int u = u0 + v;
-            if (ba[v] != pa) {
-              unsigned char* o = ga + 8u * static_cast<uint32_t>(ba[v]);
-              lds_add64(o, 0, cwr[u]);
-              lds_add64(o, kArrBytes, csr[u]);
-            }
-            if (two && bb[v] != pb) {
-              unsigned char* o = gb + 8u * static_cast<uint32_t>(bb[v]);
-              lds_add64(o, 0, cwr[u]);
-              lds_add64(o, kArrBytes, csr[u]);
-            }
-            pa = ba[v];
-            pb = bb[v];
-          }
-        }
+        if (k0 + 1 < F)
+          fold_pass<true>(smem, stride, k0, s_f, s_nb, dtr, cwr, csr, dt_before, run, lane);
+        else
+          fold_pass<false>(smem, stride, k0, s_f, s_nb, dtr, cwr, csr, dt_before, run, lane);
       }
     }
     // A point whose time step crosses more than one fine bin (a data gap) belongs
