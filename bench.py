@@ -67,8 +67,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg1")
     ap.add_argument("--stars", type=int, default=0, help="use only the first N stars of the workload")
-    ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--cpu-sample", type=int, default=768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-size kernel "
+                         "for scaling the profiler's FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -79,6 +82,16 @@ def main():
     from paper_2302_01293_amd.device import DeviceSearch
 
     assert torch.cuda.is_available(), "no GPU"
+    if args.copy_calibration_mib:
+        nel = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d MiB read + %d MiB written" % (args.copy_calibration_mib,
+                                                                  args.copy_calibration_mib))
+        del src, dst
     log("generating workload", args.workload)
     batch, desc = make_workload(args.workload)
     if args.stars and args.stars < batch.n_stars:

@@ -17,12 +17,12 @@ namespace mi355bls {
 
 // Compiled limits.
 constexpr int kThreads = 1024;        // threads per prep / S/N workgroup
-constexpr int kSearchThreads = 1024;  // threads per search workgroup (4 waves per SIMD,
-                                      // up to 128 registers per lane)
+constexpr int kSearchThreads = 512;   // threads per search workgroup; two workgroups per CU
+                                      // (4 waves per SIMD, up to 128 registers per lane)
 constexpr int kUMax = 12;             // register-resident points per search thread
-constexpr int kGBytes = 128 * 1024;   // LDS bytes for the per-frequency accumulators
-constexpr int kNbLimit = kGBytes / 32 - 32;  // largest fine-bin count: 32 B of G and D per
-                                              // bin, plus the replicated wrap bins
+constexpr int kGBytes = 64 * 1024;    // LDS bytes for the per-frequency accumulators
+constexpr int kNbLimit = kGBytes / 16 - 32;  // largest fine-bin count: 16 B per bin, plus
+                                              // the replicated wrap bins
 constexpr int kFMax = 32;             // most frequencies processed together
 constexpr int kMCap = 32;             // longest duration (in fine bins)
 constexpr int64_t kMaxPoints = int64_t(1) << 30;
@@ -71,7 +71,7 @@ struct Consts {
 };
 
 struct Layout {  // byte offsets inside the device workspace
-  int64_t stars, rt, items, gaps, dt, cw, cs, rho, total;
+  int64_t stars, rt, items, gaps, dt, cw, cs, rho, counter, total;
 };
 
 }  // namespace mi355bls

@@ -27,6 +27,7 @@
 //    every point is bit-identical to a sequential FP64 evaluation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -226,18 +227,18 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const StarDesc* __restrict
 
 // ----------------------------------------------------------------------------
 // Fused fold -> boundary accumulation -> H -> duration/phase scan.
-// One workgroup per work item (a frequency range of one star).  LDS layout for the
-// F frequencies of the current group, nb_cap bins each (k-major):
-//   [  0, 32K)  GW  int64 G of the weights     -> after conversion HW (FP64 H_W)
-//   [32K, 64K)  GS  int64 G of the residuals   -> after conversion HS (FP64 H_S)
-//   [64K, 96K)  DW  int64 range-add ends at data gaps (weights)
-//   [96K,128K)  DS  int64 range-add ends at data gaps (residuals)
-// Separate 8-byte arrays keep the boundary atomics of a wave on distinct banks,
-// and GS sits at a fixed offset from GW (one address per atomic pair).
+// A persistent grid pulls work items (a frequency range of one star) from a
+// counter; 64 KB of LDS per workgroup lets two workgroups share a CU, so one can
+// fold (LDS-atomic bound) while the other scans (VALU bound).  LDS layout for the
+// F frequencies of the current group, `stride` slots each (k-major):
+//   [  0, 32K)  GW  int64 G of the weights   -> int64 H_W -> FP64 H_W
+//   [32K, 64K)  GS  int64 G of the residuals -> int64 H_S -> FP64 H_S
+// GS sits at a fixed offset from GW, so one address serves each atomic pair.
 // ----------------------------------------------------------------------------
-constexpr int kArrBytes = kGBytes / 4;   // 32 KB per array
-constexpr int kUGroup = 4;               // points whose bins are computed together
-constexpr int kArrElems = kArrBytes / 8; // F * nb_cap <= 4096
+constexpr int kArrBytes = kGBytes / 2;    // 32 KB per array
+constexpr int kUGroup = 4;                // points whose bins are computed together
+constexpr int kArrElems = kArrBytes / 8;  // F * stride <= 4096
+constexpr int kSlotIter = kArrElems / kSearchThreads;  // slots per thread (conversion, scan)
 
 struct SearchArgs {
   const StarDesc* stars;
@@ -250,24 +251,27 @@ struct SearchArgs {
   const int64_t* windows;  // optional (star, i0, i1) triples replacing items
   double* sr;
   bls_best* best;
+  unsigned int* next;      // per-XCD work counters, kCounterStride apart (zeroed by k_reset)
+  int32_t n_items;
   Consts c;
 };
 
-// Best window of a lane or wave: power s^2 / d kept as the pair (s^2, d) so that
-// comparisons need no division; mj = (m << 20) | j orders ties lexicographically.
-// The empty state is (-1, 1, ~0): every valid window beats it.
-struct ScanBest {
-  double ss, d;
-  uint32_t mj;
-  uint32_t pad;
+// Per-group scalars after the two accumulator arrays.
+struct GroupLds {
+  double f[kFMax];
+  int32_t nb[kFMax];
+  int32_t blast[kFMax];               // bin of the last point (receives the totals)
+  unsigned long long key[kFMax];      // 1 + bits of the best power (0: no valid window)
+  uint32_t mj[kFMax];                 // smallest (m << 20 | j) reaching that power
+  int32_t item[2];
 };
+constexpr size_t kSearchLds = kGBytes + sizeof(GroupLds);
+static_assert(2 * kSearchLds <= 160 * 1024, "two search workgroups per CU");
 
 __device__ __forceinline__ bool better(double ssa, double da, uint32_t mja, double ssb, double db, uint32_t mjb) {
   const double x = ssa * db, y = ssb * da;
   return x > y || (x == y && mja < mjb);
 }
-
-constexpr int kScanUnroll = 16;  // durations up to this length run fully unrolled
 
 constexpr double kW62 = 2.168404344971008868e-19;  // 2^-62
 
@@ -282,22 +286,37 @@ __device__ __forceinline__ void lds_add64(unsigned char* base, uint32_t byte_off
   atomicAdd(reinterpret_cast<unsigned long long*>(base + byte_off), static_cast<unsigned long long>(v));
 }
 
+// Slot index -> (frequency k, bin b) for idx < F * stride <= 4096: a float
+// estimate of idx / stride corrected by one step either way.
+__device__ __forceinline__ void slot_of(int idx, int stride, float inv_stride, int& k, int& b) {
+  k = static_cast<int>(static_cast<float>(idx) * inv_stride);
+  b = idx - k * stride;
+  if (b < 0) {
+    --k;
+    b += stride;
+  } else if (b >= stride) {
+    ++k;
+    b -= stride;
+  }
+}
+
 // One pass of the fold over the wave's block for frequencies k0 and, when TWO,
 // k0 + 1: a point whose bin differs from its predecessor's is a boundary and adds
 // its prefix values into G of its bin.
 template <bool TWO>
-__device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k0, const double* s_f,
-                                          const int32_t* s_nb, const double (&dtr)[kUMax],
-                                          const long long (&cwr)[kUMax], const long long (&csr)[kUMax],
-                                          double dt_before, int run, int lane) {
+__device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k0, const GroupLds* g,
+                                          const double (&dtr)[kUMax], const long long (&cwr)[kUMax],
+                                          const long long (&csr)[kUMax], double dt_before, int run) {
   const int k1 = TWO ? k0 + 1 : k0;
-  const double fa = s_f[k0], fb = s_f[k1];
-  const double na = static_cast<double>(s_nb[k0]), nbv = static_cast<double>(s_nb[k1]);
-  const uint32_t ga = static_cast<uint32_t>(k0 * stride) * 8u;
-  const uint32_t gb = static_cast<uint32_t>(k1 * stride) * 8u;
-  // Bin of the point before the block: the predecessor of lane 0 at step 0.
-  int32_t carry_a = fold_bin_nc(dt_before, fa, na);
-  int32_t carry_b = TWO ? fold_bin_nc(dt_before, fb, nbv) : 0;
+  const double fa = g->f[k0], fb = g->f[k1];
+  const double na = static_cast<double>(g->nb[k0]), nbv = static_cast<double>(g->nb[k1]);
+  uint32_t ga = static_cast<uint32_t>(k0 * stride) * 8u;
+  uint32_t gb = static_cast<uint32_t>(k1 * stride) * 8u;
+  asm volatile("" : "+s"(ga), "+s"(gb));  // keep base + 8 b as one shift-add
+  // Bins of the previous step; lane 0 of the first step takes the bin of the point
+  // before the block (uniform).
+  int32_t prev_a = fold_bin_nc(dt_before, fa, na);
+  int32_t prev_b = TWO ? fold_bin_nc(dt_before, fb, nbv) : 0;
 #pragma unroll
   for (int u0 = 0; u0 < kUMax; u0 += kUGroup) {
     if (u0 >= run) break;
@@ -347,8 +366,8 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
     for (int v = 0; v < kUGroup; ++v) {
       const int u = u0 + v;
       // Predecessor bins: lane l-1 of this step (DPP wave shift right by one);
-      // lane 0 takes lane 63 of the previous step.
-      const int32_t la = v == 0 ? carry_a : __builtin_amdgcn_readlane(ba[v - 1], 63);
+      // lane 0 keeps the old value, lane 63 of the previous step (wave rotate).
+      const int32_t la = (v == 0 && u0 == 0) ? prev_a : __builtin_amdgcn_mov_dpp(v == 0 ? prev_a : ba[v - 1], 0x13C, 0xf, 0xf, false);
       const int32_t pa = __builtin_amdgcn_update_dpp(la, ba[v], 0x138, 0xf, 0xf, false);
       if (ba[v] != pa) {
         const uint32_t o = ga + 8u * static_cast<uint32_t>(ba[v]);
@@ -356,7 +375,7 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
         lds_add64(smem, o + kArrBytes, csr[u]);
       }
       if (TWO) {
-        const int32_t lb = v == 0 ? carry_b : __builtin_amdgcn_readlane(bb[v - 1], 63);
+        const int32_t lb = (v == 0 && u0 == 0) ? prev_b : __builtin_amdgcn_mov_dpp(v == 0 ? prev_b : bb[v - 1], 0x13C, 0xf, 0xf, false);
         const int32_t pb = __builtin_amdgcn_update_dpp(lb, bb[v], 0x138, 0xf, 0xf, false);
         if (bb[v] != pb) {
           const uint32_t o = gb + 8u * static_cast<uint32_t>(bb[v]);
@@ -365,291 +384,341 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
         }
       }
     }
-    carry_a = __builtin_amdgcn_readlane(ba[kUGroup - 1], 63);
-    if (TWO) carry_b = __builtin_amdgcn_readlane(bb[kUGroup - 1], 63);
+    prev_a = ba[kUGroup - 1];
+    if (TWO) prev_b = bb[kUGroup - 1];
   }
 }
 
-__global__ void __launch_bounds__(kSearchThreads) k_search(SearchArgs a) {
+// Work queue.  MI355X has 8 XCDs, each with its own L2, and consecutive workgroups
+// of a launch go to consecutive XCDs.  The cost-ordered item list is cut into
+// chunks of kQueueChunk items dealt round-robin to 8 queues; a workgroup drains
+// the queue of its own XCD first (blockIdx mod 8), so the items of one star, which
+// are adjacent in the list, run on one XCD and share its L2, then helps the other
+// queues.  Each queue's item index only grows, so a queue found empty stays empty
+// and every workgroup stops after at most 8 empty probes.
+constexpr int kXcds = 8;
+constexpr int kQueueChunk = 16;
+constexpr int kCounterStride = 16;  // 64 bytes between counters
+
+// Zero the work counters on the stream (a kernel, so the sequence can be captured).
+__global__ void k_reset(unsigned int* next) {
+  if (threadIdx.x < kXcds) next[threadIdx.x * kCounterStride] = 0u;
+}
+
+__global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   long long* GW = reinterpret_cast<long long*>(smem);
   long long* GS = reinterpret_cast<long long*>(smem + kArrBytes);
-  long long* DW = reinterpret_cast<long long*>(smem + 2 * kArrBytes);
-  long long* DS = reinterpret_cast<long long*>(smem + 3 * kArrBytes);
   double* HW = reinterpret_cast<double*>(smem);
   double* HS = reinterpret_cast<double*>(smem + kArrBytes);
-  double* s_f = reinterpret_cast<double*>(smem + kGBytes);
-  int32_t* s_nb = reinterpret_cast<int32_t*>(s_f + kFMax);
-  int32_t* s_blast = s_nb + kFMax;
-  long long* s_g0w = reinterpret_cast<long long*>(s_blast + kFMax);
-  long long* s_g0s = s_g0w + kFMax;
-  ScanBest* s_res = reinterpret_cast<ScanBest*>(s_g0s + kFMax);  // [kFMax][16]
+  GroupLds* g = reinterpret_cast<GroupLds*>(smem + kGBytes);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  WorkItem it;
-  if (a.windows) {
-    const int64_t* wv = a.windows + 3 * static_cast<int64_t>(blockIdx.x);
-    it.star = static_cast<int32_t>(wv[0]);
-    it.i0 = static_cast<int32_t>(wv[1]);
-    it.i1 = static_cast<int32_t>(wv[2]);
-  } else {
-    it = a.items[blockIdx.x];
-  }
-  const StarDesc d = a.stars[it.star];
-  const StarRt rt = a.rt[it.star];
-  if (it.i0 < 0) it.i0 = 0;
-  if (it.i1 > d.nf) it.i1 = static_cast<int32_t>(d.nf);
-  if (it.i1 <= it.i0) return;
-  const int64_t n = d.n;
-  const double* __restrict__ dt = a.dt + d.p_off;
-  const int64_t* __restrict__ cw = a.cw + d.p_off;
-  const int64_t* __restrict__ cs = a.cs + d.p_off;
+  const int T = kSearchThreads;
+  const int m_max = a.c.m_max;
+  const uint32_t m_mask = a.c.m_mask;
+  const bool dip = a.c.dip_only != 0;
   const int32_t noverlap = a.c.noverlap;
 
-  double f_first;
-  int32_t nb_cap;
-  grid_point(d, it.i0, noverlap, f_first, nb_cap);
-  if (nb_cap > kNbLimit || nb_cap < 1) return;  // rejected by the plan
-  // Slot stride: nb_cap bins plus room to replicate the first bins after the
-  // last, so windows that wrap past bin nb-1 read contiguously.
-  const int stride = nb_cap + kMCap;
-  const int F_act = min(kFMax, kArrElems / stride);
-
-  // Points: wave w owns a contiguous block of 64 * run points per chunk; lane l holds
-  // points block + 64 u + l, so a point's predecessor is in the previous lane of the
-  // same step (lane 0: lane 63 of the previous step).  Loads are coalesced and the
-  // boundaries of one step fall on consecutive bins.
-  const int T = blockDim.x;
-  const int run = static_cast<int>(min<int64_t>(kUMax, (n + T - 1) / T));
-  const int64_t chunk_pts = static_cast<int64_t>(run) * T;
-  const int nchunks = static_cast<int>((n + chunk_pts - 1) / chunk_pts);
-  double dtr[kUMax];
-  long long cwr[kUMax], csr[kUMax];
-  double dt_before = 0.0;  // time of the point before the wave's block (its first if none)
-  bool active = false;
-  auto load_chunk = [&](int c) {
-    const int64_t wbase = static_cast<int64_t>(c) * chunk_pts + static_cast<int64_t>(wave) * 64 * run;
-    active = wbase < n;
-    if (!active) return;
-    const int64_t wend = min<int64_t>(n, wbase + static_cast<int64_t>(64) * run);
-    // Points past the block's end repeat its last point: same bin, no boundary.
-#pragma unroll
-    for (int u = 0; u < kUMax; ++u) {
-      const int64_t q = min<int64_t>(wbase + u * 64 + lane, wend - 1);
-      dtr[u] = dt[q];
-      cwr[u] = cw[q];
-      csr[u] = cs[q];
-    }
-    dt_before = dt[wbase > 0 ? wbase - 1 : 0];
-  };
-  if (nchunks == 1) load_chunk(0);
-  const double dt_last = dt[n - 1];
-
-  const int waves = T >> 6;
-  for (int g0 = it.i0; g0 < it.i1; g0 += F_act) {
-    const int F = min(F_act, it.i1 - g0);
-    if (tid < F) {
-      double f;
-      int32_t nb;
-      grid_point(d, g0 + tid, noverlap, f, nb);
-      s_f[tid] = f;
-      s_nb[tid] = nb;
-      s_blast[tid] = fold_bin_nc(dt_last, f, static_cast<double>(nb));
-    }
-    for (int idx = tid; idx < F * stride; idx += T) {
-      GW[idx] = 0;
-      GS[idx] = 0;
-      DW[idx] = 0;
-      DS[idx] = 0;
-    }
-    __syncthreads();
-
-    // ---- fold: a point whose bin differs from its predecessor's is a boundary
-    // and adds its prefix values into G of its bin.  Two frequencies per pass give
-    // the scheduler two independent chains per point.
-    for (int c = 0; c < nchunks; ++c) {
-      if (nchunks > 1) load_chunk(c);
-      if (!active) continue;
-      for (int k0 = 0; k0 < F; k0 += 2) {
-        if (k0 + 1 < F)
-          fold_pass<true>(smem, stride, k0, s_f, s_nb, dtr, cwr, csr, dt_before, run, lane);
-        else
-          fold_pass<false>(smem, stride, k0, s_f, s_nb, dtr, cwr, csr, dt_before, run, lane);
-      }
-    }
-    // A point whose time step crosses more than one fine bin (a data gap) belongs
-    // to every bin in (bp, b]: G[b] has its prefix values from the fold; adding them
-    // to the skipped bins (bp, b-1] changes H = G[b+1] - G[b] only at the two ends
-    // of that range, recorded in D: D[bp] += E, D[b-1] -= E.  Only points in the
-    // star's gap list can do this (their step is large compared with the bin width
-    // at the top of the grid).
-    if (d.n_gaps > 0) {
-      const int32_t* gl = a.gaps + d.g_off;
-      const int total_g = F * d.n_gaps;
-      for (int idx = tid; idx < total_g; idx += T) {
-        const int k = idx / d.n_gaps;
-        const int32_t q = gl[idx - k * d.n_gaps];
-        const double f = s_f[k];
-        const int32_t nb = s_nb[k];
-        const double nbd = static_cast<double>(nb);
-        const int32_t bq = fold_bin_nc(dt[q - 1], f, nbd);
-        const int32_t bu = fold_bin_nc(dt[q], f, nbd);
-        int32_t steps = bu - bq;
-        if (steps < 0) steps += nb;
-        if (steps > 1) {
-          const int32_t bm1 = bu == 0 ? nb - 1 : bu - 1;
-          const uint32_t kb = static_cast<uint32_t>(k * stride);
-          const long long ew = cw[q], es = cs[q];
-          atomicAdd(reinterpret_cast<unsigned long long*>(&DW[kb + bq]), static_cast<unsigned long long>(ew));
-          atomicAdd(reinterpret_cast<unsigned long long*>(&DS[kb + bq]), static_cast<unsigned long long>(es));
-          atomicAdd(reinterpret_cast<unsigned long long*>(&DW[kb + bm1]), 0ull - static_cast<unsigned long long>(ew));
-          atomicAdd(reinterpret_cast<unsigned long long*>(&DS[kb + bm1]), 0ull - static_cast<unsigned long long>(es));
+  int queue = static_cast<int>(blockIdx.x % kXcds);  // used by thread 0 only
+  int probes = 0;
+  for (;;) {
+    if (tid == 0) {
+      int32_t item = -1;
+      while (probes < kXcds) {
+        const unsigned t = atomicAdd(&a.next[queue * kCounterStride], 1u);
+        const int64_t chunk = static_cast<int64_t>(t / kQueueChunk) * kXcds + queue;
+        const int64_t cand = chunk * kQueueChunk + t % kQueueChunk;
+        if (cand < a.n_items) {
+          item = static_cast<int32_t>(cand);
+          break;
         }
+        queue = (queue + 1) % kXcds;
+        ++probes;
       }
+      g->item[0] = item;
     }
     __syncthreads();
+    const int32_t item = g->item[0];
+    __syncthreads();
+    if (item < 0) break;  // every wave of the group leaves together
 
-    // ---- G -> H in place, in chunks of T bins (all reads of a chunk precede its
-    // writes; the wrap value G[k][0] is saved first) ----
-    if (tid < F) {
-      s_g0w[tid] = GW[tid * stride];
-      s_g0s[tid] = GS[tid * stride];
+    WorkItem it;
+    if (a.windows) {
+      const int64_t* wv = a.windows + 3 * static_cast<int64_t>(item);
+      it.star = static_cast<int32_t>(wv[0]);
+      it.i0 = static_cast<int32_t>(wv[1]);
+      it.i1 = static_cast<int32_t>(wv[2]);
+    } else {
+      it = a.items[item];
     }
-    __syncthreads();
-    const int total = F * stride;
-    for (int base = 0; base < total; base += T) {
-      const int idx = base + tid;
-      bool act = false;
-      double hw = 0.0, hs = 0.0;
-      if (idx < total) {
-        const int k = idx / stride;
-        const int b = idx - k * stride;
-        const int32_t nb = s_nb[k];
-        if (b < nb) {
-          act = true;
-          const unsigned long long w0 = static_cast<unsigned long long>(GW[idx] - DW[idx]);
-          const unsigned long long s0 = static_cast<unsigned long long>(GS[idx] - DS[idx]);
-          const unsigned long long w1 = static_cast<unsigned long long>(b + 1 < nb ? GW[idx + 1] : s_g0w[k]);
-          const unsigned long long s1 = static_cast<unsigned long long>(b + 1 < nb ? GS[idx + 1] : s_g0s[k]);
-          unsigned long long dw = w1 - w0, ds = s1 - s0;
-          if (b == s_blast[k]) {
-            dw += static_cast<unsigned long long>(rt.cw_total);
-            ds += static_cast<unsigned long long>(rt.cs_total);
-          }
-          hw = static_cast<double>(static_cast<long long>(dw)) * kW62;
-          hs = static_cast<double>(static_cast<long long>(ds)) * rt.s_scale;
+    const StarDesc d = a.stars[it.star];
+    const StarRt rt = a.rt[it.star];
+    if (it.i0 < 0) it.i0 = 0;
+    if (it.i1 > d.nf) it.i1 = static_cast<int32_t>(d.nf);
+    if (it.i1 <= it.i0) continue;
+    const int64_t n = d.n;
+    const double* __restrict__ dt = a.dt + d.p_off;
+    const int64_t* __restrict__ cw = a.cw + d.p_off;
+    const int64_t* __restrict__ cs = a.cs + d.p_off;
+
+    double f_first;
+    int32_t nb_cap;
+    grid_point(d, it.i0, noverlap, f_first, nb_cap);
+    if (nb_cap > kNbLimit || nb_cap < 1) continue;  // rejected by the plan
+    // Slot stride: nb_cap bins plus room to replicate the first m_max bins after
+    // the last, so windows that wrap past bin nb-1 read contiguously.
+    const int stride_i = nb_cap + m_max;
+    const float inv_stride_i = 1.0f / static_cast<float>(stride_i);
+    const int F_act = min(kFMax, kArrElems / stride_i);
+
+    // Points: wave w owns a contiguous block of 64 * run points per chunk; lane l
+    // holds points block + 64 u + l, so a point's predecessor is in the previous
+    // lane of the same step (lane 0: lane 63 of the previous step).  Loads are
+    // coalesced and the boundaries of one step fall on consecutive bins.
+    const int nchunks = static_cast<int>((n + static_cast<int64_t>(T) * kUMax - 1) / (static_cast<int64_t>(T) * kUMax));
+    const int run = static_cast<int>((n + static_cast<int64_t>(T) * nchunks - 1) / (static_cast<int64_t>(T) * nchunks));
+    const int64_t chunk_pts = static_cast<int64_t>(run) * T;
+    const double dt_last = dt[n - 1];
+
+    for (int g0 = it.i0; g0 < it.i1; g0 += F_act) {
+      const int F = min(F_act, it.i1 - g0);
+      // Per-group copies of the slot geometry: keeps the compiler from hoisting
+      // every slot's indexes out of this loop (they would stay live across the fold).
+      int stride = __builtin_amdgcn_readfirstlane(stride_i);
+      float inv_stride = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, inv_stride_i)));
+      asm volatile("" : "+s"(stride), "+s"(inv_stride));
+      if (tid < F) {
+        double f;
+        int32_t nb;
+        grid_point(d, g0 + tid, noverlap, f, nb);
+        g->f[tid] = f;
+        g->nb[tid] = nb;
+        g->blast[tid] = fold_bin_nc(dt_last, f, static_cast<double>(nb));
+        g->key[tid] = 0ull;
+        g->mj[tid] = ~0u;
+      }
+      for (int idx = tid; idx < F * stride; idx += T) {
+        GW[idx] = 0;
+        GS[idx] = 0;
+      }
+      __syncthreads();
+
+      // ---- fold: a point whose bin differs from its predecessor's is a boundary
+      // and adds its prefix values into G of its bin.  Two frequencies per pass
+      // give the scheduler two independent chains per point.
+      for (int c = 0; c < nchunks; ++c) {
+        const int64_t wbase = static_cast<int64_t>(c) * chunk_pts + static_cast<int64_t>(wave) * 64 * run;
+        if (wbase >= n) continue;
+        const int64_t wend = min<int64_t>(n, wbase + static_cast<int64_t>(64) * run);
+        double dtr[kUMax];
+        long long cwr[kUMax], csr[kUMax];
+        // Points past the block's end repeat its last point: same bin, no boundary.
+#pragma unroll
+        for (int u = 0; u < kUMax; ++u) {
+          const int64_t q = min<int64_t>(wbase + u * 64 + lane, wend - 1);
+          dtr[u] = dt[q];
+          cwr[u] = cw[q];
+          csr[u] = cs[q];
+        }
+        const double dt_before = dt[wbase > 0 ? wbase - 1 : 0];
+        for (int k0 = 0; k0 < F; k0 += 2) {
+          if (k0 + 1 < F)
+            fold_pass<true>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run);
+          else
+            fold_pass<false>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run);
         }
       }
       __syncthreads();
-      if (act) {
-        HW[idx] = hw;
-        HS[idx] = hs;
+
+      // ---- G -> H: H[b] = G[b+1] - G[b] (+ the totals at the last point's bin;
+      // G[nb] is G[0]), one wave per frequency, in place.  A wave converts 64 bins
+      // at a time: it reads G[b] and G[b+1] of a chunk before writing the chunk, and
+      // the next chunk's first bin is still unconverted then (a wave's LDS accesses
+      // run in program order); G[0] is read before chunk 0 is written.  Without
+      // data gaps the result goes straight to FP64 with the first bins replicated
+      // after the last (windows wrap past nb - 1); otherwise int64 H first.
+      const bool gaps = d.n_gaps > 0;
+      for (int k = wave; k < F; k += kSearchThreads / 64) {
+        const int32_t nb = g->nb[k], bl = g->blast[k];
+        const int mrep = min(m_max, nb - 1);
+        long long* gw = GW + k * stride;
+        long long* gs = GS + k * stride;
+        const long long g0w = gw[0], g0s = gs[0];
+        for (int b0 = 0; b0 < nb; b0 += 64) {
+          const int b = b0 + lane;
+          if (b < nb) {
+            const long long nw = b + 1 < nb ? gw[b + 1] : g0w;
+            const long long ns = b + 1 < nb ? gs[b + 1] : g0s;
+            unsigned long long dw = static_cast<unsigned long long>(nw) - static_cast<unsigned long long>(gw[b]);
+            unsigned long long ds = static_cast<unsigned long long>(ns) - static_cast<unsigned long long>(gs[b]);
+            if (b == bl) {
+              dw += static_cast<unsigned long long>(rt.cw_total);
+              ds += static_cast<unsigned long long>(rt.cs_total);
+            }
+            if (gaps) {
+              gw[b] = static_cast<long long>(dw);
+              gs[b] = static_cast<long long>(ds);
+            } else {
+              const double vw = static_cast<double>(static_cast<long long>(dw)) * kW62;
+              const double vs = static_cast<double>(static_cast<long long>(ds)) * rt.s_scale;
+              double* hw = reinterpret_cast<double*>(gw);
+              double* hs = reinterpret_cast<double*>(gs);
+              hw[b] = vw;
+              hs[b] = vs;
+              if (b < mrep) {
+                hw[nb + b] = vw;
+                hs[nb + b] = vs;
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (gaps) {
+        // A point whose time step crosses more than one fine bin (a data gap)
+        // belongs to every bin in (bp, b]: G[b] got its prefix values from the
+        // fold; adding them to the skipped bins (bp, b-1] too changes H only at the
+        // two ends of that range: H[bp] += E, H[b-1] -= E.  Only points in the
+        // star's gap list can do this (their step is large compared with the bin
+        // width at the top of the grid).
+        const int32_t* gl = a.gaps + d.g_off;
+        const int total_g = F * d.n_gaps;
+        for (int idx = tid; idx < total_g; idx += T) {
+          const int k = idx / d.n_gaps;
+          const int32_t q = gl[idx - k * d.n_gaps];
+          const double f = g->f[k];
+          const int32_t nb = g->nb[k];
+          const double nbd = static_cast<double>(nb);
+          const int32_t bq = fold_bin_nc(dt[q - 1], f, nbd);
+          const int32_t bu = fold_bin_nc(dt[q], f, nbd);
+          int32_t steps = bu - bq;
+          if (steps < 0) steps += nb;
+          if (steps > 1) {
+            const int32_t bm1 = bu == 0 ? nb - 1 : bu - 1;
+            const uint32_t kb = static_cast<uint32_t>(k * stride);
+            const long long ew = cw[q], es = cs[q];
+            atomicAdd(reinterpret_cast<unsigned long long*>(&GW[kb + bq]), static_cast<unsigned long long>(ew));
+            atomicAdd(reinterpret_cast<unsigned long long*>(&GS[kb + bq]), static_cast<unsigned long long>(es));
+            atomicAdd(reinterpret_cast<unsigned long long*>(&GW[kb + bm1]), 0ull - static_cast<unsigned long long>(ew));
+            atomicAdd(reinterpret_cast<unsigned long long*>(&GS[kb + bm1]), 0ull - static_cast<unsigned long long>(es));
+          }
+        }
+        __syncthreads();
+        // int64 H -> FP64 H in place, with the wrap replication.
+        for (int idx = tid; idx < F * stride; idx += T) {
+          int k, b;
+          slot_of(idx, stride, inv_stride, k, b);
+          const int32_t nb = g->nb[k];
+          if (b < nb) {
+            const double vw = static_cast<double>(GW[idx]) * kW62;
+            const double vs = static_cast<double>(GS[idx]) * rt.s_scale;
+            HW[idx] = vw;
+            HS[idx] = vs;
+            if (b < min(m_max, nb - 1)) {
+              HW[idx + nb] = vw;
+              HS[idx + nb] = vs;
+            }
+          }
+        }
+        __syncthreads();
+      }
+
+      // ---- scan: slot (k, j) = every duration m of the ladder starting at bin j.
+      // A slot keeps its best window with the power s^2 / (r (1 - r)) compared as
+      // cross products (no division); the group's best per frequency is then the
+      // largest power (an integer maximum on its IEEE bits) and, among slots that
+      // reach it, the smallest (m, j).
+      unsigned long long skey[kSlotIter];
+      uint32_t smj[kSlotIter];
+#pragma unroll
+      for (int r = 0; r < kSlotIter; ++r) {
+        const int idx = tid + r * T;
+        int k, j;
+        slot_of(idx, stride, inv_stride, k, j);
+        skey[r] = 0ull;
+        smj[r] = ~0u;
+        if (k < F && j < g->nb[k]) {
+          const int32_t nb = g->nb[k];
+          const int mlim = min(m_max, nb - 1);
+          const double* hwk = HW + idx;
+          const double* hsk = HS + idx;
+          double bss = -1.0, bd = 1.0;
+          uint32_t bmj = ~0u;
+          double rr = 0.0, ss0 = 0.0;
+          auto window = [&](int m, double rv, double sv) {
+            const double dd = fma(-rv, rv, rv);  // r (1 - r) > 0  <=>  0 < r < 1
+            const double ss = sv * sv;
+            const uint32_t mj = (static_cast<uint32_t>(m) << 20) | static_cast<uint32_t>(j);
+            const bool ok = dd > 0.0 && (!dip || sv < 0.0);
+            if (ok && better(ss, dd, mj, bss, bd, bmj)) {
+              bss = ss;
+              bd = dd;
+              bmj = mj;
+            }
+          };
+#pragma unroll
+          for (int m = 1; m <= 12; ++m) {
+            if (m <= mlim) {
+              rr += hwk[m - 1];
+              ss0 += hsk[m - 1];
+              if (m_mask & (1u << (m - 1))) window(m, rr, ss0);
+            }
+          }
+          for (int m = 13; m <= mlim; ++m) {
+            rr += hwk[m - 1];
+            ss0 += hsk[m - 1];
+            if (m_mask & (1u << (m - 1))) window(m, rr, ss0);
+          }
+          if (bmj != ~0u) {
+            const double p = bss / bd;
+            skey[r] = static_cast<unsigned long long>(__double_as_longlong(p)) + 1ull;
+            smj[r] = bmj;
+            atomicMax(&g->key[k], skey[r]);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kSlotIter; ++r) {
+        if (skey[r] != 0ull) {
+          int k, j;
+          slot_of(tid + r * T, stride, inv_stride, k, j);
+          if (skey[r] == g->key[k]) atomicMin(&g->mj[k], smj[r]);
+        }
+      }
+      __syncthreads();
+      if (tid < F) {
+        const int k = tid;
+        const int64_t fi = d.f_off + g0 + k;
+        bls_best bb;
+        bb.m = 0;
+        bb.j = -1;
+        bb.r = 0.0;
+        bb.s = 0.0;
+        double sr = 0.0;
+        const uint32_t mj = g->mj[k];
+        if (g->key[k] != 0ull && mj != ~0u) {
+          const int m = static_cast<int>(mj >> 20), j = static_cast<int>(mj & 0xFFFFFu);
+          const double* hwk = HW + k * stride;
+          const double* hsk = HS + k * stride;
+          double r = 0.0, s = 0.0;
+          for (int u = 0; u < m; ++u) {
+            r += hwk[j + u];
+            s += hsk[j + u];
+          }
+          sr = sqrt((s * s) / (r * (1.0 - r)));
+          bb.m = m;
+          bb.j = j;
+          bb.r = r;
+          bb.s = s;
+        }
+        a.sr[fi] = sr;
+        if (a.best) a.best[fi] = bb;
       }
       __syncthreads();
     }
-
-    // Replicate the first bins after the last one (windows wrap past nb - 1).
-    const int m_max = a.c.m_max;
-    for (int idx = tid; idx < F * kMCap; idx += T) {
-      const int k = idx / kMCap;
-      const int i = idx - k * kMCap;
-      const int32_t nb = s_nb[k];
-      if (i < min(m_max, nb - 1)) {
-        HW[k * stride + nb + i] = HW[k * stride + i];
-        HS[k * stride + nb + i] = HS[k * stride + i];
-      }
-    }
-    __syncthreads();
-
-    // ---- scan: every start bin j, durations m of the ladder.  Branch-free running
-    // maximum of s^2 / (r (1 - r)) compared as cross products. ----
-    const int wpk = F <= waves ? waves / F : 1;  // waves per frequency
-    const int kstep = waves / wpk;
-    const uint32_t m_mask = a.c.m_mask;
-    const bool dip = a.c.dip_only != 0;
-    for (int k = wave / wpk; k < F; k += kstep) {
-      const int sub = wave - (wave / wpk) * wpk;
-      const int32_t nb = s_nb[k];
-      const double* hwk = HW + k * stride;
-      const double* hsk = HS + k * stride;
-      double bss = -1.0, bd = 1.0;
-      uint32_t bmj = ~0u;
-      const int mlim = min(m_max, nb - 1);
-      auto window = [&](int m, int j, double r, double s) {
-        const double dd = fma(-r, r, r);  // r (1 - r) > 0  <=>  0 < r < 1
-        const double ss = s * s;
-        const uint32_t mj = (static_cast<uint32_t>(m) << 20) | static_cast<uint32_t>(j);
-        const bool ok = dd > 0.0 && (!dip || s < 0.0);
-        if (ok && better(ss, dd, mj, bss, bd, bmj)) {
-          bss = ss;
-          bd = dd;
-          bmj = mj;
-        }
-      };
-      for (int j = sub * 64 + lane; j < nb; j += wpk * 64) {
-        double r = 0.0, s = 0.0;
-#pragma unroll
-        for (int m = 1; m <= kScanUnroll; ++m) {
-          if (m <= mlim) {
-            r += hwk[j + m - 1];
-            s += hsk[j + m - 1];
-            if (m_mask & (1u << (m - 1))) window(m, j, r, s);
-          }
-        }
-        for (int m = kScanUnroll + 1; m <= mlim; ++m) {
-          r += hwk[j + m - 1];
-          s += hsk[j + m - 1];
-          if (m_mask & (1u << (m - 1))) window(m, j, r, s);
-        }
-      }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double qss = __shfl_xor(bss, o, 64);
-        const double qd = __shfl_xor(bd, o, 64);
-        const uint32_t qmj = __shfl_xor(bmj, o, 64);
-        if (better(qss, qd, qmj, bss, bd, bmj)) {
-          bss = qss;
-          bd = qd;
-          bmj = qmj;
-        }
-      }
-      if (lane == 0) s_res[k * 16 + sub] = ScanBest{bss, bd, bmj, 0u};
-    }
-    __syncthreads();
-    if (tid < F) {
-      const int k = tid;
-      ScanBest bsel = s_res[k * 16];
-      for (int q = 1; q < wpk; ++q) {
-        const ScanBest o = s_res[k * 16 + q];
-        if (better(o.ss, o.d, o.mj, bsel.ss, bsel.d, bsel.mj)) bsel = o;
-      }
-      const int64_t fi = d.f_off + g0 + k;
-      bls_best bb;
-      bb.m = 0;
-      bb.j = -1;
-      bb.r = 0.0;
-      bb.s = 0.0;
-      double sr = 0.0;
-      if (bsel.mj != ~0u) {
-        const int m = static_cast<int>(bsel.mj >> 20), j = static_cast<int>(bsel.mj & 0xFFFFFu);
-        const double* hwk = HW + k * stride;
-        const double* hsk = HS + k * stride;
-        double r = 0.0, s = 0.0;
-        for (int u = 0; u < m; ++u) {
-          r += hwk[j + u];
-          s += hsk[j + u];
-        }
-        sr = sqrt((s * s) / (r * (1.0 - r)));
-        bb.m = m;
-        bb.j = j;
-        bb.r = r;
-        bb.s = s;
-      }
-      a.sr[fi] = sr;
-      if (a.best) a.best[fi] = bb;
-    }
-    __syncthreads();
   }
 }
 
@@ -720,12 +789,20 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
   a.windows = d_windows;
   a.sr = d_sr;
   a.best = d_best;
+  a.next = reinterpret_cast<unsigned int*>(base + L.counter);
   a.c = plan->consts;
   const int64_t n_items = d_windows ? n_windows : static_cast<int64_t>(plan->items.size());
   if (n_items == 0) return BLS_OK;
-  const size_t lds = kGBytes + kFMax * (8 + 4 + 4 + 8 + 8) + kFMax * 16 * sizeof(ScanBest);
-  static_assert(kGBytes + kFMax * 32 + kFMax * 16 * sizeof(ScanBest) <= 160 * 1024, "LDS budget");
-  hipLaunchKernelGGL(k_search, dim3(static_cast<unsigned>(n_items)), dim3(kSearchThreads), lds, st, a);
+  a.n_items = static_cast<int32_t>(n_items);
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return BLS_E_HIP;
+  // Persistent grid: two workgroups per CU pull items until the counter passes the end.
+  const int64_t grid = std::min<int64_t>(n_items, 2 * static_cast<int64_t>(cus));
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);  // 8 counters
+  if (hipGetLastError() != hipSuccess) return BLS_E_HIP;
+  hipLaunchKernelGGL(k_search, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds, st, a);
   if (hipGetLastError() != hipSuccess) return BLS_E_HIP;
   return BLS_OK;
 }
