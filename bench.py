@@ -29,6 +29,34 @@ FP64_OPS_PEAK = 256 * 64 * 2.4e9
 OPS_PER_CELL = 4  # DMUL (dt f), FRACT, DMUL (phase nb), CVT (bin index)
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "k_search_cfg1_counters.json")
+
+
+def search_sources_digest() -> str:
+    """Digest of the sources that define the search kernel (counters go stale when
+    they change)."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in ("paper_2302_01293_amd/csrc/search.hip", "paper_2302_01293_amd/csrc/plan.hpp"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per k_search launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (scaled by a plain copy's readings), if they were taken on this
+    workload with the current kernel sources; else None."""
+    try:
+        with open(COUNTERS) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if c.get("workload") != workload or c.get("source_sha256") != search_sources_digest():
+        return None
+    return float(c["bytes_per_launch"])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -155,7 +183,8 @@ def main():
         "cells_per_s": cells / (srch * 1e-3),
         "kernel_ms": {"prepare": prep, "search": srch, "snr": snr},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(args.workload) if not args.stars else None,
                      "kernel": "k_search (fold + boundary accumulation + scan)"},
     }
     if not args.no_cpu_baseline:

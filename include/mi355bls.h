@@ -72,6 +72,8 @@ typedef struct bls_params {
                           1: FP64 phase, FP32 compensated bin sums (fast path) */
   double a_min_rstar;  /* minimum a/R*: 2 (Sectors 61+) or 3 (Sectors 59-60) */
   double sector_days;  /* gap length that splits continuous stretches (27.4) */
+  int64_t tile_cells;  /* target points x frequencies per work item; 0 = library default
+                          (6 Mi); an autotuner may pick another (results do not change) */
 } bls_params;
 
 /* Per-star inputs. */
@@ -165,8 +167,11 @@ bls_status bls_prepare(bls_plan* plan, void* d_workspace, const double* d_t, con
  *   d_sr   [n_freq_total]  SR per frequency;
  *   d_best [n_freq_total]  best window per frequency (nullable).
  * d_windows (nullable) restricts the search to n_windows triples
- * (star, i_begin, i_end) of int64 (device); frequencies outside them are not
- * written.  NULL searches every star's full grid. */
+ * (star, i_begin, i_end) of int64 (device, row-major [n_windows][3]); each range is
+ * clipped to [0, nf) of its star, triples naming no star of the plan are skipped,
+ * and frequencies outside the ranges are not written.  NULL searches every star's
+ * full grid; a non-NULL list with n_windows = 0 does nothing.  The per-frequency
+ * results do not depend on how the grid is split into ranges. */
 bls_status bls_search_batch(bls_plan* plan, void* d_workspace, const int64_t* d_windows,
                             int64_t n_windows, double* d_sr, bls_best* d_best, bls_stream_t stream);
 

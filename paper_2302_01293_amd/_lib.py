@@ -28,7 +28,8 @@ class BlsParams(ctypes.Structure):
                 ("qmax_fac", ctypes.c_double), ("dlogq", ctypes.c_double),
                 ("noverlap", ctypes.c_int32), ("dip_only", ctypes.c_int32),
                 ("mad_of_raw", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("a_min_rstar", ctypes.c_double), ("sector_days", ctypes.c_double)]
+                ("a_min_rstar", ctypes.c_double), ("sector_days", ctypes.c_double),
+                ("tile_cells", ctypes.c_int64)]
 
 
 class BlsStar(ctypes.Structure):

@@ -61,7 +61,7 @@ double freq_at(const StarDesc& d, int64_t i) {
 bool valid_params(const bls_params& p) {
   return p.spp > 0.0 && p.qmin_fac > 0.0 && p.qmax_fac >= p.qmin_fac && p.dlogq > 0.0 &&
          p.noverlap >= 1 && p.a_min_rstar > 0.0 && p.sector_days > 0.0 &&
-         (p.precision == 0 || p.precision == 1) && std::isfinite(p.spp) &&
+         (p.precision == 0 || p.precision == 1) && p.tile_cells >= 0 && std::isfinite(p.spp) &&
          std::isfinite(p.qmin_fac) && std::isfinite(p.qmax_fac) && std::isfinite(p.dlogq);
 }
 
@@ -237,7 +237,7 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
   // Work items: frequency tiles of each star sized to a similar number of cells
   // (points x frequencies), ordered by cost, largest first, so that the tail of
   // the launch is made of small items.
-  const int64_t target_cells = int64_t(6) << 20;
+  const int64_t target_cells = p->tile_cells > 0 ? p->tile_cells : int64_t(6) << 20;
   try {
     for (int32_t s = 0; s < n_stars; ++s) {
       const StarDesc& d = plan->stars[s];

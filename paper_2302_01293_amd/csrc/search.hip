@@ -253,6 +253,7 @@ struct SearchArgs {
   bls_best* best;
   unsigned int* next;      // per-XCD work counters, kCounterStride apart (zeroed by k_reset)
   int32_t n_items;
+  int32_t n_stars;
   Consts c;
 };
 
@@ -446,18 +447,21 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
 
     WorkItem it;
     if (a.windows) {
+      // Caller triples: a star outside the batch is skipped, the range is clipped
+      // to the star's grid (in 64 bits, before narrowing).
       const int64_t* wv = a.windows + 3 * static_cast<int64_t>(item);
-      it.star = static_cast<int32_t>(wv[0]);
-      it.i0 = static_cast<int32_t>(wv[1]);
-      it.i1 = static_cast<int32_t>(wv[2]);
+      const int64_t ws = wv[0];
+      if (ws < 0 || ws >= a.n_stars) continue;
+      const int64_t nfs = a.stars[ws].nf;
+      it.star = static_cast<int32_t>(ws);
+      it.i0 = static_cast<int32_t>(max<int64_t>(0, min<int64_t>(wv[1], nfs)));
+      it.i1 = static_cast<int32_t>(max<int64_t>(0, min<int64_t>(wv[2], nfs)));
     } else {
       it = a.items[item];
     }
+    if (it.i1 <= it.i0) continue;
     const StarDesc d = a.stars[it.star];
     const StarRt rt = a.rt[it.star];
-    if (it.i0 < 0) it.i0 = 0;
-    if (it.i1 > d.nf) it.i1 = static_cast<int32_t>(d.nf);
-    if (it.i1 <= it.i0) continue;
     const int64_t n = d.n;
     const double* __restrict__ dt = a.dt + d.p_off;
     const int64_t* __restrict__ cw = a.cw + d.p_off;
@@ -794,6 +798,7 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
   const int64_t n_items = d_windows ? n_windows : static_cast<int64_t>(plan->items.size());
   if (n_items == 0) return BLS_OK;
   a.n_items = static_cast<int32_t>(n_items);
+  a.n_stars = plan->n_stars;
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)

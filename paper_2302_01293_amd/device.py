@@ -51,6 +51,13 @@ class DeviceSearch:
                           None if self.w is None else self.w.data_ptr(), stream=_stream_handle(stream))
 
     def run_search(self, stream=None, windows=None):
+        """Full grid, or only the (star, i0, i1) frequency ranges of an int64 [n, 3]
+        device tensor (ranges are clipped to the star's grid; empty ones are skipped;
+        outputs outside the ranges are left untouched).  An empty work list does nothing
+        (the C call treats a NULL list as the full grid, and an empty tensor has no
+        storage)."""
+        if windows is not None and int(windows.shape[0]) == 0:
+            return
         h = _stream_handle(stream)
         self.plan.search(self.ws_ptr, self.sr.data_ptr(), None if self.best is None else self.best.data_ptr(),
                          None if windows is None else windows.data_ptr(),
@@ -61,10 +68,25 @@ class DeviceSearch:
         self.plan.snr(self.ws_ptr, self.sr.data_ptr(), None if self.best is None else self.best.data_ptr(),
                       None if self.snr is None else self.snr.data_ptr(), self.result.data_ptr(), stream=h)
 
-    def run(self, stream=None):
+    def run(self, stream=None, windows=None):
         self.run_prepare(stream)
-        self.run_search(stream)
+        self.run_search(stream, windows)
         self.run_snr(stream)
+
+    def capture(self, windows=None):
+        """Record prepare -> search -> S/N into a HIP graph (``torch.cuda.CUDAGraph``).
+
+        The library allocates nothing and records no memset (the work counters are
+        cleared by a kernel), so the sequence is capturable; ``graph.replay()``
+        recomputes every output from the current contents of the input tensors.
+        """
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=side):
+            self.run(windows=windows)
+        torch.cuda.current_stream().wait_stream(side)
+        return g
 
     # ---- host copies ----
     def sr_host(self) -> np.ndarray:

@@ -1,0 +1,116 @@
+"""GPU tests of the batching layer: HIP-graph capture and replay, restricted
+frequency ranges (work lists of (star, i0, i1)), and the largest fine-bin count the
+search kernel accepts."""
+import numpy as np
+import pytest
+
+from paper_2302_01293_amd import synth
+
+import parity_util as pu
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def test_graph_replay_matches_eager():
+    import torch
+    b = synth.ragged(6, start=60)
+    _say("case graph replay: 6 ragged stars")
+    ds = pu.run_gpu(b)
+    sr_e = ds.sr_host()
+    res_e = ds.result.cpu().numpy().copy()
+    snr_e = ds.snr_host()
+    g = ds.capture()
+    torch.cuda.synchronize()
+    other = pu.run_gpu(synth.ragged(2, start=70))  # unrelated eager work between replays
+    for rep in range(3):
+        ds.sr.zero_()
+        ds.snr.zero_()
+        ds.result.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(ds.sr_host().view(np.uint64), sr_e.view(np.uint64)), rep
+        assert np.array_equal(ds.snr_host().view(np.uint64), snr_e.view(np.uint64)), rep
+        assert np.array_equal(ds.result.cpu().numpy(), res_e), rep
+        other.run()
+        torch.cuda.synchronize()
+
+
+def test_windows_match_full_grid():
+    import torch
+    b = synth.ragged(5, start=80)
+    _say("case windows: 5 ragged stars")
+    ds = pu.run_gpu(b)
+    full = ds.sr_host()
+    best_full = ds.best_host().copy()
+    nfs = np.diff(ds.plan.freq_offsets)
+    rng = np.random.default_rng(5)
+    tri = []
+    for s in range(b.n_stars):
+        for _ in range(3):
+            i0 = int(rng.integers(0, nfs[s]))
+            i1 = int(min(nfs[s], i0 + rng.integers(1, 700)))
+            tri.append((s, i0, i1))
+    tri.append((0, 5, 5))                      # empty range
+    tri.append((1, nfs[1] - 3, nfs[1] + 50))   # clipped at the end of the grid
+    tri.append((2, -10, 7))                    # clipped at the start
+    tri.append((99, 0, 10))                    # no such star: skipped
+    tri.append((-1, 0, 10))
+    wins = torch.tensor(np.array(tri, np.int64), device="cuda")
+    ds.sr.fill_(-1.0)
+    ds.run_search(windows=wins)
+    torch.cuda.synchronize()
+    part = ds.sr_host()
+    best_part = ds.best_host()
+    covered = np.zeros(len(full), bool)
+    for s, i0, i1 in tri:
+        if not 0 <= s < b.n_stars:
+            continue
+        i0, i1 = max(0, i0), min(nfs[s], i1)
+        if i1 > i0:
+            covered[ds.plan.freq_offsets[s] + i0: ds.plan.freq_offsets[s] + i1] = True
+    assert np.array_equal(part[covered].view(np.uint64), full[covered].view(np.uint64))
+    assert np.array_equal(best_part[covered], best_full[covered])
+    assert np.all(part[~covered] == -1.0)
+    # an empty work list launches nothing and leaves the outputs alone
+    ds.run_search(windows=torch.zeros((0, 3), dtype=torch.int64, device="cuda"))
+    torch.cuda.synchronize()
+    assert np.array_equal(ds.sr_host().view(np.uint64), part.view(np.uint64))
+
+
+def test_largest_bin_count(oracle):
+    # a two-year baseline at 12-h cadence searched from 50 d to 350 d: the
+    # first frequency has ~3990 fine bins, next to the compiled limit
+    t = np.concatenate([synth.sector_times([s], 0.5) for s in range(26)])
+    rng = np.random.default_rng(9)
+    y = 1.0 + rng.normal(0, 1e-3, len(t))
+    w = np.full(len(t), 1e6)
+    b = synth.Batch(t, y, w, np.array([0, len(t)]), np.array([1.0]), np.array([50.0]), np.array([350.0]))
+    ds = pu.fetch(pu.run_gpu(b))
+    f, nb = ds.plan.frequencies(0)
+    _say("case largest nb: points", len(t), "nb0", int(nb[0]), "frequencies", len(f))
+    from paper_2302_01293_amd import _lib
+    assert 3900 <= nb[0] <= _lib.limits()["nb_max"]
+    orc = pu.run_oracle(oracle, b)
+    pu.compare_star(ds, orc, 0, 0, b.star(0), "largest-nb")
+
+
+def test_autotune_picks_a_candidate_and_results_do_not_change(tmp_path):
+    import torch
+    from paper_2302_01293_amd import autotune, _lib
+    b = synth.ragged(8, start=90)
+    _say("case autotune: 8 ragged stars")
+    cands = (1 << 18, 1 << 21, 1 << 24)
+    out = autotune.tune(b, candidates=cands, n_sample=8, reps=2, cache_path=str(tmp_path / "tune.json"))
+    assert out["tile_cells"] in cands and not out["cached"]
+    again = autotune.tune(b, candidates=cands, n_sample=8, reps=2, cache_path=str(tmp_path / "tune.json"))
+    assert again["cached"] and again["tile_cells"] == out["tile_cells"]
+    ref = pu.run_gpu(b)
+    for c in cands:
+        ds = pu.run_gpu(b, _lib.default_params(tile_cells=c))
+        assert np.array_equal(ds.sr_host().view(np.uint64), ref.sr_host().view(np.uint64)), c
+        assert np.array_equal(ds.results_host(), ref.results_host()), c

@@ -116,3 +116,37 @@ def test_limits():
     lim = _lib.limits()
     # 26-sector baselines at solar density reach ~4000 fine bins
     assert lim["nb_max"] >= 4000 and lim["m_max"] >= 12
+
+
+def test_bin_count_beyond_limit_rejected():
+    # a two-year baseline up to 400 d at solar density needs ~4300 fine bins
+    t = np.concatenate([synth.sector_times([s], 0.5) for s in range(26)])
+    y = np.ones_like(t)
+    with pytest.raises(_lib.BlsError) as e:
+        _lib.Plan(t, y, np.ones_like(t), np.array([0, len(t)]), np.array([1.0]), np.array([50.0]),
+                  np.array([400.0]))
+    assert e.value.code == -7
+
+
+def test_tile_size_changes_only_the_work_list():
+    b = synth.ragged(4, start=3)
+    small = _plan_for(b, tile_cells=1 << 18)
+    big = _plan_for(b, tile_cells=1 << 26)
+    assert small.workspace_bytes > big.workspace_bytes  # more work items
+    for s in range(b.n_stars):
+        fa, na = small.frequencies(s)
+        fb, nbb = big.frequencies(s)
+        assert np.array_equal(fa, fb) and np.array_equal(na, nbb)
+
+
+def test_autotune_cache_and_sampling(tmp_path):
+    from paper_2302_01293_amd import autotune
+    pts = np.array([100, 5000, 20000, 150000, 12000] * 100)
+    idx = autotune.sample_stars(pts, 16)
+    assert len(idx) <= 16 and pts[idx].min() == pts.min() and pts[idx].max() == pts.max()
+    k1 = autotune.shape_key("gfx950", pts)
+    assert k1 == autotune.shape_key("gfx950", pts[::-1].copy())
+    path = str(tmp_path / "t.json")
+    assert autotune.load_cache(path) == {}
+    autotune.save_cache(path, {k1: {"tile_cells": 123}})
+    assert autotune.load_cache(path)[k1]["tile_cells"] == 123
