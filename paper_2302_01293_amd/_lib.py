@@ -20,7 +20,16 @@ STATUS_NAMES = {0: "BLS_OK", -1: "BLS_E_ARG", -2: "BLS_E_INPUT", -3: "BLS_E_EMPT
 
 EXPORTS = ("bls_default_params", "bls_plan_create", "bls_plan_query", "bls_plan_star_info",
            "bls_plan_frequencies", "bls_plan_durations", "bls_plan_upload", "bls_prepare", "bls_search_batch",
-           "bls_snr", "bls_plan_destroy", "bls_status_string", "bls_limits")
+           "bls_snr", "bls_plan_destroy", "bls_status_string", "bls_limits",
+           # learned period proposal (include/mi355pp.h)
+           "pp_act_bytes", "pp_resample", "pp_forward", "pp_backward", "pp_adam", "pp_propose",
+           "pp_snr_windows")
+
+PP_NPARAM = 3122
+PP_NCLASS = 513
+PP_NBINS_IN = 4096
+PP_MAX_WINDOWS = 10
+PP_ACT_BYTES_PER_STAR = 106496
 
 
 class BlsParams(ctypes.Structure):
@@ -93,6 +102,21 @@ def lib():
         L.bls_status_string.argtypes = [i32]
         L.bls_limits.restype = i32
         L.bls_limits.argtypes = [vp]
+        f32 = ctypes.c_float
+        L.pp_act_bytes.restype = i32
+        L.pp_act_bytes.argtypes = [i32, ctypes.POINTER(i64)]
+        L.pp_resample.restype = i32
+        L.pp_resample.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.pp_forward.restype = i32
+        L.pp_forward.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.pp_backward.restype = i32
+        L.pp_backward.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp]
+        L.pp_adam.restype = i32
+        L.pp_adam.argtypes = [vp, vp, vp, vp, i32, f32, vp]
+        L.pp_propose.restype = i32
+        L.pp_propose.argtypes = [vp, vp, vp, i32, f32, vp, vp, vp, vp]
+        L.pp_snr_windows.restype = i32
+        L.pp_snr_windows.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -212,3 +236,9 @@ class Plan:
         st = lib().bls_snr(self.h, d_ws, d_sr, d_best or None, d_snr or None, d_result, stream or None)
         if st != BLS_OK:
             raise BlsError("bls_snr", st)
+
+
+def check(name: str, st: int):
+    """Raise BlsError unless a library call returned BLS_OK."""
+    if st != BLS_OK:
+        raise BlsError(name, st)

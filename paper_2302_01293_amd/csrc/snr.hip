@@ -18,6 +18,7 @@
 #include <cstdint>
 
 #include "plan.hpp"
+#include "select.hpp"
 
 namespace mi355bls {
 
@@ -36,142 +37,21 @@ __device__ __forceinline__ double freq_s(const StarDesc& d, int64_t i) {
   return (u * u) * u;
 }
 
-// Order-preserving 64-bit keys of doubles (NaN excluded by construction).
-__device__ __forceinline__ unsigned long long key_of(double v) {
-  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
-  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
-}
-__device__ __forceinline__ double value_of(unsigned long long k) {
-  const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
-  return __longlong_as_double(static_cast<long long>(b));
-}
-
-struct SelShared {
-  unsigned int hist[256];
-  unsigned long long prefix;
-  long long rank;
-  int digit;
-};
-
-// The rank-th smallest (0-based) of v(i) for i in [lo, hi), exact.
-template <typename F>
-__device__ double block_select(F v, int64_t lo, int64_t hi, int64_t rank, SelShared& sh) {
-  const int tid = threadIdx.x, T = blockDim.x, lane = tid & 63;
-  unsigned long long prefix = 0;
-  for (int shift = 56; shift >= 0; shift -= 8) {
-    for (int q = tid; q < 256; q += T) sh.hist[q] = 0;
-    __syncthreads();
-    const unsigned long long hmask = shift == 56 ? 0ull : (~0ull << (shift + 8));
-    for (int64_t i0 = lo; i0 < hi; i0 += T) {
-      const int64_t i = i0 + tid;
-      bool take = false;
-      int dg = 0;
-      if (i < hi) {
-        const unsigned long long k = key_of(v(i));
-        take = (k & hmask) == (prefix & hmask);
-        dg = static_cast<int>((k >> shift) & 255ull);
-      }
-      // Aggregate the common case where a whole wave falls into one bucket.
-      const unsigned long long m = __ballot(take);
-      if (m) {
-        const int leader = __ffsll(static_cast<long long>(m)) - 1;
-        const int ld = __shfl(dg, leader, 64);
-        const unsigned long long same = __ballot(take && dg == ld);
-        if (same == m) {
-          if (lane == leader) atomicAdd(&sh.hist[ld], static_cast<unsigned>(__popcll(m)));
-        } else if (take) {
-          atomicAdd(&sh.hist[dg], 1u);
-        }
-      }
-    }
-    __syncthreads();
-    if (tid < 64) {
-      unsigned int c0 = sh.hist[4 * tid], c1 = sh.hist[4 * tid + 1], c2 = sh.hist[4 * tid + 2],
-                   c3 = sh.hist[4 * tid + 3];
-      long long mine = static_cast<long long>(c0) + c1 + c2 + c3;
-      long long incl = mine;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const long long y = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += y;
-      }
-      const long long excl = incl - mine;
-      const long long r = rank;
-      if (r >= excl && r < incl) {
-        long long acc = excl;
-        int dsel = 4 * tid;
-        if (r >= acc + c0) { acc += c0; dsel++;
-          if (r >= acc + c1) { acc += c1; dsel++;
-            if (r >= acc + c2) { acc += c2; dsel++; } } }
-        sh.digit = dsel;
-        sh.rank = r - acc;
-      }
-    }
-    __syncthreads();
-    prefix |= static_cast<unsigned long long>(sh.digit) << shift;
-    rank = sh.rank;
-    __syncthreads();
-  }
-  return value_of(prefix);
-}
-
-template <typename F>
-__device__ double block_median(F v, int64_t lo, int64_t hi, SelShared& sh) {
-  const int64_t c = hi - lo;
-  if (c & 1) return block_select(v, lo, hi, c / 2, sh);
-  const double a = block_select(v, lo, hi, c / 2 - 1, sh);
-  const double b = block_select(v, lo, hi, c / 2, sh);
-  return (a + b) * 0.5;
-}
-
-struct ArgMax {
-  double v;
-  int64_t i;
-};
-
-__device__ __forceinline__ ArgMax amax(ArgMax a, ArgMax b) {
-  return (b.v > a.v || (b.v == a.v && b.i < a.i)) ? b : a;
-}
-
-__device__ ArgMax block_argmax(ArgMax x, ArgMax* scratch) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    ArgMax y;
-    y.v = __shfl_xor(x.v, o, 64);
-    y.i = __shfl_xor(x.i, o, 64);
-    x = amax(x, y);
-  }
-  __syncthreads();
-  if (lane == 0) scratch[wave] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    ArgMax r = scratch[0];
-    for (int q = 1; q < (blockDim.x >> 6); ++q) r = amax(r, scratch[q]);
-    scratch[0] = r;
-  }
-  __syncthreads();
-  const ArgMax r = scratch[0];
-  __syncthreads();
-  return r;
-}
-
 }  // namespace
 
-__global__ void __launch_bounds__(kThreads) k_snr(const StarDesc* __restrict__ stars, const double* __restrict__ sr_all,
-                                                  const bls_best* __restrict__ best_all, double* __restrict__ snr_all,
-                                                  double* __restrict__ rho_all, bls_result* __restrict__ res_all,
-                                                  Consts c) {
-  __shared__ SelShared sh;
-  __shared__ int64_t s_start[kMaxSturges + 1];
-  __shared__ double s_kx[kMaxSturges], s_ky[kMaxSturges];
-  __shared__ int s_nk;
-  __shared__ ArgMax s_red[16];
+// Median-binned trend of one star's SR spectrum: Sturges bins in frequency, a knot
+// at the centre of every non-empty bin holding the bin's median SR.
+struct TrendLds {
+  SelShared sh;
+  int64_t start[kMaxSturges + 1];
+  double kx[kMaxSturges], ky[kMaxSturges];
+  int nk;
+  ArgMax red[16];
+};
+
+__device__ void build_knots(const StarDesc& d, const double* __restrict__ sr, TrendLds& L) {
   const int tid = threadIdx.x, T = blockDim.x;
-  const StarDesc d = stars[blockIdx.x];
   const int64_t nf = d.nf;
-  const double* __restrict__ sr = sr_all + d.f_off;
-  double* __restrict__ rho = rho_all + d.f_off;
   const int nbins = d.sturges;
   const double f0 = freq_s(d, 0);
   const double span = freq_s(d, nf - 1) - f0;
@@ -182,52 +62,102 @@ __global__ void __launch_bounds__(kThreads) k_snr(const StarDesc* __restrict__ s
     if (k < 0) k = 0;
     return k;
   };
-  // Bin b covers indices [s_start[b], s_start[b+1]) (bins are monotone in i).
-  for (int b = tid; b <= nbins; b += T) s_start[b] = nf;
+  // Bin b covers indices [start[b], start[b+1]) (bins are monotone in i).
+  for (int b = tid; b <= nbins; b += T) L.start[b] = nf;
   __syncthreads();
   for (int64_t i = tid; i < nf; i += T) {
     const int k = bin_of(i);
     const int kp = i > 0 ? bin_of(i - 1) : -1;
-    for (int b = kp + 1; b <= k; ++b) s_start[b] = i;
+    for (int b = kp + 1; b <= k; ++b) L.start[b] = i;
   }
   __syncthreads();
-  if (tid == 0) s_nk = 0;
+  if (tid == 0) L.nk = 0;
   __syncthreads();
   auto srv = [&](int64_t i) { return sr[i]; };
   for (int b = 0; b < nbins; ++b) {
-    const int64_t lo = s_start[b], hi = s_start[b + 1];
+    const int64_t lo = L.start[b], hi = L.start[b + 1];
     if (hi <= lo) continue;
-    const double med = block_median(srv, lo, hi, sh);
+    const double med = block_median(srv, lo, hi, L.sh);
     if (tid == 0) {
-      s_kx[s_nk] = f0 + ((static_cast<double>(b) + 0.5) * span) / static_cast<double>(nbins);
-      s_ky[s_nk] = med;
-      s_nk = s_nk + 1;
+      L.kx[L.nk] = f0 + ((static_cast<double>(b) + 0.5) * span) / static_cast<double>(nbins);
+      L.ky[L.nk] = med;
+      L.nk = L.nk + 1;
     }
     __syncthreads();
   }
-  const int nk = s_nk;
-  // Trend by linear interpolation, residual rho = SR - trend.
-  auto trend_at = [&](double f) -> double {
-    if (f <= s_kx[0]) return s_ky[0];
-    if (f >= s_kx[nk - 1]) return s_ky[nk - 1];
-    int q = 0;
-    while (q + 1 < nk && s_kx[q + 1] <= f) ++q;
-    const double slope = (s_ky[q + 1] - s_ky[q]) / (s_kx[q + 1] - s_kx[q]);
-    return slope * (f - s_kx[q]) + s_ky[q];
-  };
-  for (int64_t i = tid; i < nf; i += T) rho[i] = sr[i] - trend_at(freq_s(d, i));
+}
+
+// Linear interpolation through the knots, constant beyond the first and last.
+__device__ double trend_at(const TrendLds& L, double f) {
+  const int nk = L.nk;
+  if (f <= L.kx[0]) return L.ky[0];
+  if (f >= L.kx[nk - 1]) return L.ky[nk - 1];
+  int q = 0;
+  while (q + 1 < nk && L.kx[q + 1] <= f) ++q;
+  const double slope = (L.ky[q + 1] - L.ky[q]) / (L.kx[q + 1] - L.kx[q]);
+  return slope * (f - L.kx[q]) + L.ky[q];
+}
+
+// Residual rho = SR - trend into the scratch array, and sigma = 1.4826 MAD.
+__device__ double residual_sigma(const StarDesc& d, const double* __restrict__ sr, double* __restrict__ rho,
+                                 TrendLds& L, int mad_of_raw) {
+  const int tid = threadIdx.x, T = blockDim.x;
+  const int64_t nf = d.nf;
+  for (int64_t i = tid; i < nf; i += T) rho[i] = sr[i] - trend_at(L, freq_s(d, i));
   __syncthreads();
+  auto srv = [&](int64_t i) { return sr[i]; };
   auto rhov = [&](int64_t i) { return rho[i]; };
-  double med, sigma;
-  if (c.mad_of_raw) {
-    med = block_median(srv, 0, nf, sh);
+  if (mad_of_raw) {
+    const double med = block_median(srv, 0, nf, L.sh);
     auto dev = [&](int64_t i) { return fabs(sr[i] - med); };
-    sigma = 1.4826 * block_median(dev, 0, nf, sh);
-  } else {
-    med = block_median(rhov, 0, nf, sh);
-    auto dev = [&](int64_t i) { return fabs(rho[i] - med); };
-    sigma = 1.4826 * block_median(dev, 0, nf, sh);
+    return 1.4826 * block_median(dev, 0, nf, L.sh);
   }
+  const double med = block_median(rhov, 0, nf, L.sh);
+  auto dev = [&](int64_t i) { return fabs(rho[i] - med); };
+  return 1.4826 * block_median(dev, 0, nf, L.sh);
+}
+
+// Summary of the chosen frequency i of a star (period, T0, duration, depth).
+__device__ bls_result make_result(const StarDesc& d, const double* sr, const bls_best* best_all, const TrendLds& L,
+                                  int64_t i, int64_t i_sr, double snr, double sigma, int status, int nbins,
+                                  int32_t noverlap) {
+  bls_result r;
+  double f;
+  int32_t nb;
+  grid_point_s(d, i, noverlap, f, nb);
+  r.i_snr = i;
+  r.i_sr = i_sr;
+  r.period = 1.0 / f;
+  r.sr = sr[i];
+  r.snr = snr;
+  r.trend = trend_at(L, f);
+  r.sigma = sigma;
+  r.status = status;
+  r.nbins = nbins;
+  r.t0 = r.duration = r.depth = NAN;
+  if (best_all) {
+    const bls_best b = best_all[d.f_off + i];
+    if (b.j >= 0) {
+      double ph = (static_cast<double>(b.j) + 0.5 * static_cast<double>(b.m)) / static_cast<double>(nb);
+      ph = ph - floor(ph);
+      r.t0 = d.t0 + ph / f;
+      r.duration = (static_cast<double>(b.m) / static_cast<double>(nb)) / f;
+      r.depth = -b.s / (b.r * (1.0 - b.r));
+    }
+  }
+  return r;
+}
+
+// Plain S/N of one star over its full grid.
+__device__ void snr_full(const StarDesc& d, const double* __restrict__ sr_all, const bls_best* __restrict__ best_all,
+                         double* __restrict__ snr_all, double* __restrict__ rho_all, bls_result* out, const Consts& c,
+                         TrendLds& L) {
+  const int tid = threadIdx.x, T = blockDim.x;
+  const int64_t nf = d.nf;
+  const double* __restrict__ sr = sr_all + d.f_off;
+  double* __restrict__ rho = rho_all + d.f_off;
+  build_knots(d, sr, L);
+  const double sigma = residual_sigma(d, sr, rho, L, c.mad_of_raw);
   const int status = (!(sigma > 0.0) || isinf(sigma)) ? 1 : 0;
   ArgMax bs{-INFINITY, 0}, bsr{-INFINITY, 0};
   for (int64_t i = tid; i < nf; i += T) {
@@ -236,35 +166,64 @@ __global__ void __launch_bounds__(kThreads) k_snr(const StarDesc* __restrict__ s
     bs = amax(bs, ArgMax{v, i});
     bsr = amax(bsr, ArgMax{sr[i], i});
   }
-  bs = block_argmax(bs, s_red);
-  bsr = block_argmax(bsr, s_red);
-  if (tid == 0) {
-    bls_result r;
-    const int64_t i = bs.i;
-    double f;
-    int32_t nb;
-    grid_point_s(d, i, c.noverlap, f, nb);
-    r.i_snr = i;
-    r.i_sr = bsr.i;
-    r.period = 1.0 / f;
-    r.sr = sr[i];
-    r.snr = bs.v;
-    r.trend = trend_at(f);
-    r.sigma = sigma;
-    r.status = status;
-    r.nbins = nbins;
-    r.t0 = r.duration = r.depth = NAN;
-    if (best_all) {
-      const bls_best b = best_all[d.f_off + i];
-      if (b.j >= 0) {
-        double ph = (static_cast<double>(b.j) + 0.5 * static_cast<double>(b.m)) / static_cast<double>(nb);
-        ph = ph - floor(ph);
-        r.t0 = d.t0 + ph / f;
-        r.duration = (static_cast<double>(b.m) / static_cast<double>(nb)) / f;
-        r.depth = -b.s / (b.r * (1.0 - b.r));
-      }
+  bs = block_argmax(bs, L.red);
+  bsr = block_argmax(bsr, L.red);
+  if (tid == 0) *out = make_result(d, sr, best_all, L, bs.i, bsr.i, bs.v, sigma, status, d.sturges, c.noverlap);
+}
+
+__global__ void __launch_bounds__(kThreads) k_snr(const StarDesc* __restrict__ stars, const double* __restrict__ sr_all,
+                                                  const bls_best* __restrict__ best_all, double* __restrict__ snr_all,
+                                                  double* __restrict__ rho_all, bls_result* __restrict__ res_all,
+                                                  Consts c) {
+  __shared__ TrendLds L;
+  const StarDesc d = stars[blockIdx.x];
+  snr_full(d, sr_all, best_all, snr_all, rho_all, res_all + blockIdx.x, c, L);
+}
+
+// S/N restricted to frequency windows: trend and sigma come from a coarse spectrum
+// of the same star (a grid with fewer samples per peak), and S/N = (SR - trend) /
+// sigma is evaluated only at the fine frequencies inside the star's windows.  A
+// star flagged for fallback has its full fine spectrum and gets the plain S/N.
+__global__ void __launch_bounds__(kThreads) k_snr_windows(
+    const StarDesc* __restrict__ fine, const StarDesc* __restrict__ coarse, const double* __restrict__ sr_all,
+    const bls_best* __restrict__ best_all, double* __restrict__ rho_fine, const double* __restrict__ sr_coarse_all,
+    double* __restrict__ rho_coarse, const int64_t* __restrict__ windows, int32_t per_star,
+    const uint8_t* __restrict__ fallback, bls_result* __restrict__ res_all, Consts c) {
+  __shared__ TrendLds L;
+  const int s = blockIdx.x;
+  const int tid = threadIdx.x, T = blockDim.x;
+  const StarDesc d = fine[s];
+  if (fallback[s]) {
+    snr_full(d, sr_all, best_all, nullptr, rho_fine, res_all + s, c, L);
+    return;
+  }
+  const StarDesc dc = coarse[s];
+  const double* __restrict__ src = sr_coarse_all + dc.f_off;
+  build_knots(dc, src, L);
+  const double sigma = residual_sigma(dc, src, rho_coarse + dc.f_off, L, c.mad_of_raw);
+  const int status = (!(sigma > 0.0) || isinf(sigma)) ? 1 : 0;
+  const double* __restrict__ sr = sr_all + d.f_off;
+  ArgMax bs{-INFINITY, -1}, bsr{-INFINITY, -1};
+  for (int q = 0; q < per_star; ++q) {
+    const int64_t* w = windows + 3 * (static_cast<int64_t>(s) * per_star + q);
+    if (w[0] != s) continue;
+    const int64_t i0 = max<int64_t>(0, w[1]), i1 = min<int64_t>(d.nf, w[2]);
+    for (int64_t i = i0 + tid; i < i1; i += T) {
+      const double v = status ? 0.0 : (sr[i] - trend_at(L, freq_s(d, i))) / sigma;
+      bs = amax(bs, ArgMax{v, i});
+      bsr = amax(bsr, ArgMax{sr[i], i});
     }
-    res_all[blockIdx.x] = r;
+  }
+  bs = block_argmax(bs, L.red);
+  bsr = block_argmax(bsr, L.red);
+  if (tid == 0) {
+    if (bs.i < 0) {  // no window frequency: nothing searched
+      bls_result r = make_result(d, sr, nullptr, L, 0, 0, 0.0, sigma, 2, dc.sturges, c.noverlap);
+      r.sr = 0.0;
+      res_all[s] = r;
+    } else {
+      res_all[s] = make_result(d, sr, best_all, L, bs.i, bsr.i, bs.v, sigma, status, dc.sturges, c.noverlap);
+    }
   }
 }
 
@@ -282,6 +241,26 @@ extern "C" bls_status bls_snr(bls_plan* plan, void* ws, const double* d_sr, cons
   hipLaunchKernelGGL(k_snr, dim3(plan->n_stars), dim3(kThreads), 0, st,
                      reinterpret_cast<const StarDesc*>(base + L.stars), d_sr, d_best, d_snr,
                      reinterpret_cast<double*>(base + L.rho), d_result, plan->consts);
+  if (hipGetLastError() != hipSuccess) return BLS_E_HIP;
+  return BLS_OK;
+}
+
+extern "C" bls_status pp_snr_windows(const bls_plan* fine, void* fine_ws, const double* d_sr, const bls_best* d_best,
+                                     const bls_plan* coarse, void* coarse_ws, const double* d_coarse_sr,
+                                     const int64_t* d_windows, int32_t windows_per_star, const uint8_t* d_fallback,
+                                     bls_result* d_result, bls_stream_t stream) {
+  if (!fine || !coarse || !d_sr || !d_coarse_sr || !d_windows || !d_fallback || !d_result) return BLS_E_ARG;
+  if (windows_per_star < 1 || fine->n_stars != coarse->n_stars) return BLS_E_ARG;
+  if (!fine_ws || fine->uploaded_to != fine_ws || !coarse_ws || coarse->uploaded_to != coarse_ws) return BLS_E_STATE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* fb = static_cast<char*>(fine_ws);
+  char* cb = static_cast<char*>(coarse_ws);
+  hipLaunchKernelGGL(k_snr_windows, dim3(fine->n_stars), dim3(kThreads), 0, st,
+                     reinterpret_cast<const StarDesc*>(fb + fine->layout.stars),
+                     reinterpret_cast<const StarDesc*>(cb + coarse->layout.stars), d_sr, d_best,
+                     reinterpret_cast<double*>(fb + fine->layout.rho), d_coarse_sr,
+                     reinterpret_cast<double*>(cb + coarse->layout.rho), d_windows, windows_per_star, d_fallback,
+                     d_result, fine->consts);
   if (hipGetLastError() != hipSuccess) return BLS_E_HIP;
   return BLS_OK;
 }

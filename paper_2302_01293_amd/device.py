@@ -22,15 +22,21 @@ class DeviceSearch:
     """Plain BLS + S/N over a packed batch resident in HBM."""
 
     def __init__(self, t, y, w, offsets, rho=None, pmin=None, pmax=None, params=None,
-                 device: str = "cuda", want_snr: bool = True, want_best: bool = True):
+                 device: str = "cuda", want_snr: bool = True, want_best: bool = True, inputs=None):
+        """``inputs`` (optional): device tensors (t, y, w) already holding the same
+        packed arrays, shared instead of copied (e.g. by a second plan of the same
+        batch)."""
         if not torch.cuda.is_available():
             raise RuntimeError("DeviceSearch needs a GPU (HIP device)")
         self.plan = Plan(t, y, w, offsets, rho, pmin, pmax, params)
         dev = torch.device(device)
         self.device = dev
-        self.t = torch.as_tensor(np.ascontiguousarray(t, np.float64)).to(dev)
-        self.y = torch.as_tensor(np.ascontiguousarray(y, np.float64)).to(dev)
-        self.w = None if w is None else torch.as_tensor(np.ascontiguousarray(w, np.float64)).to(dev)
+        if inputs is not None:
+            self.t, self.y, self.w = inputs
+        else:
+            self.t = torch.as_tensor(np.ascontiguousarray(t, np.float64)).to(dev)
+            self.y = torch.as_tensor(np.ascontiguousarray(y, np.float64)).to(dev)
+            self.w = None if w is None else torch.as_tensor(np.ascontiguousarray(w, np.float64)).to(dev)
         nws = (self.plan.workspace_bytes + 255) // 256 * 256
         self.ws = torch.empty(nws + 256, dtype=torch.uint8, device=dev)
         base = self.ws.data_ptr()

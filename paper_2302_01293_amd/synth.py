@@ -228,6 +228,50 @@ def config4(n_stars: int = 65536, start: int = 0) -> Batch:
     return _collect(rows)
 
 
+def config3(n_stars: int = 200_000, start: int = 0, cadence: float = CADENCE_200S,
+            max_sectors: int = 13, inj_frac: float = 0.7) -> Batch:
+    """Training / evaluation light curves of the period-proposal network: a span of
+    1..max_sectors sectors (later sectors present with probability 0.8), noise and
+    density as config1, and in inj_frac of the stars a trapezoid with P log-uniform
+    in [0.5, min(100, baseline/2)] d, depth log-uniform in [3e-4, 1e-2], ingress
+    fraction U[0, 0.5] of the duration and impact parameter U[0, 0.9]."""
+    rows = []
+    for rng in _star_rngs("cfg3", n_stars, start):
+        sectors = _sector_pattern(rng, max_sectors, 0.8)
+        t = sector_times(sectors, cadence)
+        sig = float(np.exp(rng.uniform(np.log(2e-4), np.log(5e-3))))
+        rho = _density(rng)
+        y = 1.0 + rng.normal(0.0, sig, len(t))
+        inj = bool(rng.uniform() < inj_frac)
+        P = epoch = depth = dur = q_in = b = np.nan
+        if inj:
+            hi = min(100.0, 0.5 * (t[-1] - t[0]))
+            P = float(np.exp(rng.uniform(np.log(0.5), np.log(hi))))
+            depth = float(np.exp(rng.uniform(np.log(3e-4), np.log(1e-2))))
+            q_in = float(rng.uniform(0.0, 0.5))
+            b = float(rng.uniform(0.0, 0.9))
+            dur = central_duration(P, rho, b)
+            epoch = float(t[0] + rng.uniform(0.0, P))
+            y -= trapezoid(t, P, epoch, dur, depth, q_in)
+        w = np.full(len(t), 1.0 / sig**2)
+        rows.append((t, y, w, rho, dict(injected=inj, period=P, epoch=epoch, depth=depth, duration=dur,
+                                        sigma=sig, n_sectors=len(sectors), q_in=q_in, impact=b)))
+    return _collect(rows)
+
+
+def pp_init_params(seed: int = 0) -> np.ndarray:
+    """Initial FP32 parameters of the period-proposal network (random numbers only):
+    W1[16][2][16] ~ N(0, 1/32), b1 = 0, W2[16][16][8] ~ N(0, 1/128), b2 = 0,
+    w3[16] ~ N(0, 1/16), alpha = 4, beta = 0, delta = 0 (3122 values)."""
+    rng = np.random.default_rng(np.random.SeedSequence([ROOT_SEED, 7, seed]))
+    parts = [rng.normal(0.0, math.sqrt(1.0 / 32.0), 16 * 2 * 16), np.zeros(16),
+             rng.normal(0.0, math.sqrt(1.0 / 128.0), 16 * 16 * 8), np.zeros(16),
+             rng.normal(0.0, 0.25, 16), [4.0], np.zeros(512), [0.0]]
+    th = np.concatenate([np.asarray(p, np.float64) for p in parts]).astype(np.float32)
+    assert th.size == 3122
+    return th
+
+
 def ragged(n_stars: int = 12, start: int = 0, cadence: float = CADENCE_30MIN,
            max_sectors: int = 3) -> Batch:
     """Small ragged batch for tests: 1..max_sectors sector spans with missing

@@ -18,9 +18,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_functions():
-    src = open(os.path.join(ROOT, "include", "mi355bls.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(bls_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in ("mi355bls.h", "mi355pp.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b((?:bls|pp)_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_matches_binding():
