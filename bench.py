@@ -88,6 +88,19 @@ def cpu_baseline(batch, n_sample: int, seed: int = 7):
                        % (len(sample), S, dt))
 
 
+def learned_vs_plain(batch, conf: float, topk: int):
+    """Recovery of the plain detections and device-time ratio of the learned path
+    (committed trained weights) on the benchmark's own stars."""
+    from paper_2302_01293_amd import learned
+    path = os.path.join(ROOT, "paper_2302_01293_amd", "pp_weights.npy")
+    net = learned.ProposalNet(np.load(path))
+    r, _, _ = learned.time_paths(batch, net, reps=3, conf=conf, topk=topk)
+    r.update(conf=conf, topk=topk, weights="paper_2302_01293_amd/pp_weights.npy")
+    log("learned: recovery %d/%d, speed-up %.2fx, fallback %.3f, searched %.3f" % (
+        r["recovered"], r["plain_detections"], r["speedup"], r["fallback_fraction"], r["searched_fraction"]))
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +110,10 @@ def main():
     ap.add_argument("--stars", type=int, default=0, help="use only the first N stars of the workload")
     ap.add_argument("--cpu-sample", type=int, default=768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-proposal comparison (trained weights vs the plain path)")
+    ap.add_argument("--learned-conf", type=float, default=0.95)
+    ap.add_argument("--learned-topk", type=int, default=12)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size kernel "
                          "for scaling the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -187,6 +204,9 @@ def main():
                      "traffic": measured_traffic(args.workload) if not args.stars else None,
                      "kernel": "k_search (fold + boundary accumulation + scan)"},
     }
+    if not args.no_learned:
+        log("learned proposal vs plain on the same stars ...")
+        out["learned"] = learned_vs_plain(batch, args.learned_conf, args.learned_topk)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) on a sample ...")
         out["cpu_baseline"] = cpu_baseline(batch, args.cpu_sample)

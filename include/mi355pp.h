@@ -33,7 +33,7 @@ extern "C" {
 #define PP_NPARAM 3122              /* network parameters */
 #define PP_NCLASS 513               /* 512 period bins + the null class */
 #define PP_NBINS_IN 4096            /* resampled bins per light curve */
-#define PP_MAX_WINDOWS 10           /* window triples per star written by pp_propose */
+#define PP_MAX_WINDOWS 16           /* window triples per star written by pp_propose */
 #define PP_ACT_BYTES_PER_STAR 106496 /* saved activations per star (training) */
 
 /* Bytes of saved activations for a batch (pp_forward's d_act, pp_backward). */
@@ -75,12 +75,23 @@ bls_status pp_adam(float* d_theta, float* d_m, float* d_v, const float* d_grad, 
  * conf: the maximal runs of selected bins and, when Pmax > 100 d, [100 d, Pmax],
  * clipped to [Pmin, Pmax] and mapped to frequency-index ranges of the plan's grid
  * (i from ceil((cbrt(1/P_hi) - u_min)/A) to floor((cbrt(1/P_lo) - u_min)/A)).
- * Else the full grid and d_fallback[s] = 1.  Output d_windows [n_stars]
- * [PP_MAX_WINDOWS][3] int64 (star, i_begin, i_end) triples for bls_search_batch,
- * unused rows have star = -1; d_conf [n_stars] (nullable) gets c.
+ * Else the full grid and d_fallback[s] = 1.
+ * Outputs (device, caller-owned):
+ *   d_windows [n_stars][PP_MAX_WINDOWS][3] int64 (star, i_begin, i_end) triples,
+ *             unused rows star = -1 (input of pp_snr_windows);
+ *   d_fallback [n_stars] uint8;  d_conf [n_stars] FP32 (nullable) gets c;
+ *   d_tiles (nullable) [pp_tile_capacity][3] int64: the same windows cut into the
+ *             plan's work-item size (star s owns a fixed slot range, unused slots
+ *             star = -1), the work list to pass to bls_search_batch with
+ *             n_windows = pp_tile_capacity, so long windows and fallback grids are
+ *             shared by many workgroups.
  * 1 <= topk <= PP_MAX_WINDOWS - 2. */
 bls_status pp_propose(const bls_plan* plan, void* d_workspace, const float* d_logits, int32_t topk, float conf,
-                      int64_t* d_windows, uint8_t* d_fallback, float* d_conf, bls_stream_t stream);
+                      int64_t* d_windows, uint8_t* d_fallback, float* d_conf, int64_t* d_tiles,
+                      bls_stream_t stream);
+
+/* Rows of the tiled work list of pp_propose for a plan. */
+bls_status pp_tile_capacity(const bls_plan* plan, int64_t* n);
 
 /* S/N of a windowed search.  For a star with d_fallback[s] = 0: trend and sigma of
  * Sec. 2.2 item 1 come from the SR spectrum d_coarse_sr of plan `coarse` (the same

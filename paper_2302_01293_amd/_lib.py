@@ -23,12 +23,12 @@ EXPORTS = ("bls_default_params", "bls_plan_create", "bls_plan_query", "bls_plan_
            "bls_snr", "bls_plan_destroy", "bls_status_string", "bls_limits",
            # learned period proposal (include/mi355pp.h)
            "pp_act_bytes", "pp_resample", "pp_forward", "pp_backward", "pp_adam", "pp_propose",
-           "pp_snr_windows")
+           "pp_tile_capacity", "pp_snr_windows")
 
 PP_NPARAM = 3122
 PP_NCLASS = 513
 PP_NBINS_IN = 4096
-PP_MAX_WINDOWS = 10
+PP_MAX_WINDOWS = 16
 PP_ACT_BYTES_PER_STAR = 106496
 
 
@@ -114,7 +114,9 @@ def lib():
         L.pp_adam.restype = i32
         L.pp_adam.argtypes = [vp, vp, vp, vp, i32, f32, vp]
         L.pp_propose.restype = i32
-        L.pp_propose.argtypes = [vp, vp, vp, i32, f32, vp, vp, vp, vp]
+        L.pp_propose.argtypes = [vp, vp, vp, i32, f32, vp, vp, vp, vp, vp]
+        L.pp_tile_capacity.restype = i32
+        L.pp_tile_capacity.argtypes = [vp, ctypes.POINTER(i64)]
         L.pp_snr_windows.restype = i32
         L.pp_snr_windows.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp]
         _lib = L

@@ -243,6 +243,9 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
       const StarDesc& d = plan->stars[s];
       int64_t per = std::max<int64_t>(32, target_cells / std::max<int64_t>(1, d.n));
       per = std::min<int64_t>(per, 4096);
+      plan->stars[s].per_tile = static_cast<int32_t>(per);
+      plan->stars[s].tile_off = plan->tile_capacity;
+      plan->tile_capacity += (d.nf + per - 1) / per + kWindowSlack;
       for (int64_t i0 = 0; i0 < d.nf; i0 += per) {
         const int64_t i1 = std::min<int64_t>(d.nf, i0 + per);
         plan->items.push_back(WorkItem{s, static_cast<int32_t>(i0), static_cast<int32_t>(i1), 0});

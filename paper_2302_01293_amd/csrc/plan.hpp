@@ -27,6 +27,9 @@ constexpr int kFMax = 32;             // most frequencies processed together
 constexpr int kMCap = 32;             // longest duration (in fine bins)
 constexpr int64_t kMaxPoints = int64_t(1) << 30;
 constexpr int kMaxSturges = 64;
+constexpr int kWindowSlack = 16;      // extra tiles per star in a tiled window list (one
+                                      // per disjoint window: a window adds at most one
+                                      // partial tile)
 
 // Per-star descriptor (device copy is read-only).
 struct StarDesc {
@@ -41,11 +44,12 @@ struct StarDesc {
   int32_t nb0;      // fine bins at i = 0 (the largest of the star)
   int32_t sturges;  // Sturges bin count of the S/N trend
   int32_t n_gaps;   // points whose time step can cross more than one fine bin
-  int32_t pad0;
+  int32_t per_tile; // frequencies per work item of this star
   int64_t g_off;    // first entry of this star in the gap list
   double T, pmin, pmax, krho;  // descriptive (host queries)
+  int64_t tile_off; // first slot of this star in a tiled window list (see pp_propose)
 };
-static_assert(sizeof(StarDesc) == 120, "StarDesc layout");
+static_assert(sizeof(StarDesc) == 128, "StarDesc layout");
 
 // Per-star values written by the preparation kernel.
 struct StarRt {
@@ -85,6 +89,7 @@ struct bls_plan {
   std::vector<mi355bls::WorkItem> items;
   std::vector<int32_t> gaps;  // per star (CSR by StarDesc::g_off): point indices n >= 1
   std::vector<int64_t> freq_offsets;
+  int64_t tile_capacity = 0;  // slots of a tiled window list: per star, its tiles + 16
   std::vector<int32_t> durations;
   mi355bls::Consts consts{};
   mi355bls::Layout layout{};

@@ -555,9 +555,12 @@ __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* 
 // ----------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) k_propose(const StarDesc* __restrict__ stars, const float* __restrict__ logits,
                                                 int32_t topk, float conf, int64_t* __restrict__ windows,
-                                                uint8_t* __restrict__ fallback, float* __restrict__ conf_out) {
+                                                uint8_t* __restrict__ fallback, float* __restrict__ conf_out,
+                                                int64_t* __restrict__ tiles) {
   __shared__ uint8_t sel[kNpb];
   __shared__ double pr[kNpb + 1];
+  __shared__ int64_t s_w0[PP_MAX_WINDOWS], s_w1[PP_MAX_WINDOWS], s_cum[PP_MAX_WINDOWS + 1];
+  __shared__ int s_nw;
   const int s = blockIdx.x, lane = threadIdx.x;
   const StarDesc d = stars[s];
   const float* z = logits + static_cast<int64_t>(s) * (kNpb + 1);
@@ -602,50 +605,80 @@ __global__ void __launch_bounds__(64) k_propose(const StarDesc* __restrict__ sta
   for (int o = 32; o > 0; o >>= 1) mass += __shfl_xor(mass, o, 64);
   const double c = pr[kNpb] + mass;
   int64_t* wo = windows + static_cast<int64_t>(s) * PP_MAX_WINDOWS * 3;
-  if (lane != 0) return;
-  if (conf_out) conf_out[s] = static_cast<float>(c);
-  int nw = 0;
-  auto emit = [&](int64_t i0, int64_t i1) {
-    if (nw < PP_MAX_WINDOWS && i1 > i0) {
-      wo[3 * nw] = s;
-      wo[3 * nw + 1] = i0;
-      wo[3 * nw + 2] = i1;
-      ++nw;
-    }
-  };
-  const bool fb = !(c >= static_cast<double>(conf));
-  fallback[s] = fb ? 1 : 0;
-  if (fb) {
-    emit(0, d.nf);
-  } else {
-    auto range = [&](double plo, double phi) {
-      plo = fmax(plo, d.pmin);
-      phi = fmin(phi, d.pmax);
-      if (!(phi > plo)) return;
-      const double flo = 1.0 / phi, fhi = 1.0 / plo;
-      const double a = ceil((cbrt(flo) - d.umin) / d.A);
-      const double e = floor((cbrt(fhi) - d.umin) / d.A);
-      const int64_t i0 = a < 0.0 ? 0 : static_cast<int64_t>(a);
-      const int64_t i1 = e > static_cast<double>(d.nf - 1) ? d.nf - 1 : static_cast<int64_t>(e);
-      if (e >= 0.0 && i1 >= i0) emit(i0, i1 + 1);
-    };
-    int k = 0;
-    while (k < kNpb) {
-      if (sel[k]) {
-        int k1 = k;
-        while (k1 + 1 < kNpb && sel[k1 + 1]) ++k1;
-        range(period_edge(k), period_edge(k1 + 1));
-        k = k1 + 1;
-      } else {
-        ++k;
+  if (lane == 0) {
+    if (conf_out) conf_out[s] = static_cast<float>(c);
+    int nw = 0;
+    auto emit = [&](int64_t i0, int64_t i1) {
+      if (nw < PP_MAX_WINDOWS && i1 > i0) {
+        wo[3 * nw] = s;
+        wo[3 * nw + 1] = i0;
+        wo[3 * nw + 2] = i1;
+        s_w0[nw] = i0;
+        s_w1[nw] = i1;
+        ++nw;
       }
+    };
+    const bool fb = !(c >= static_cast<double>(conf));
+    fallback[s] = fb ? 1 : 0;
+    if (fb) {
+      emit(0, d.nf);
+    } else {
+      auto range = [&](double plo, double phi) {
+        plo = fmax(plo, d.pmin);
+        phi = fmin(phi, d.pmax);
+        if (!(phi > plo)) return;
+        const double flo = 1.0 / phi, fhi = 1.0 / plo;
+        const double a = ceil((cbrt(flo) - d.umin) / d.A);
+        const double e = floor((cbrt(fhi) - d.umin) / d.A);
+        const int64_t i0 = a < 0.0 ? 0 : static_cast<int64_t>(a);
+        const int64_t i1 = e > static_cast<double>(d.nf - 1) ? d.nf - 1 : static_cast<int64_t>(e);
+        if (e >= 0.0 && i1 >= i0) emit(i0, i1 + 1);
+      };
+      int k = 0;
+      while (k < kNpb) {
+        if (sel[k]) {
+          int k1 = k;
+          while (k1 + 1 < kNpb && sel[k1 + 1]) ++k1;
+          range(period_edge(k), period_edge(k1 + 1));
+          k = k1 + 1;
+        } else {
+          ++k;
+        }
+      }
+      if (d.pmax > kPbHi) range(kPbHi, d.pmax);
     }
-    if (d.pmax > kPbHi) range(kPbHi, d.pmax);
+    for (int q = nw; q < PP_MAX_WINDOWS; ++q) {
+      wo[3 * q] = -1;
+      wo[3 * q + 1] = 0;
+      wo[3 * q + 2] = 0;
+    }
+    s_cum[0] = 0;
+    for (int q = 0; q < nw; ++q) s_cum[q + 1] = s_cum[q] + (s_w1[q] - s_w0[q] + d.per_tile - 1) / d.per_tile;
+    s_nw = nw;
   }
-  for (int q = nw; q < PP_MAX_WINDOWS; ++q) {
-    wo[3 * q] = -1;
-    wo[3 * q + 1] = 0;
-    wo[3 * q + 2] = 0;
+  __syncthreads();
+  if (!tiles) return;
+  // The same windows cut into the star's work-item size, in the star's slots of the
+  // tiled list (the windows are disjoint, so they need at most ceil(nf / per) + one
+  // partial tile per window slots); unused slots have star = -1.
+  const int64_t per = d.per_tile;
+  const int64_t cap = (d.nf + per - 1) / per + mi355bls::kWindowSlack;
+  const int nw = s_nw;
+  const int64_t total = s_cum[nw];
+  int64_t* to = tiles + 3 * d.tile_off;
+  for (int64_t j = lane; j < cap; j += 64) {
+    if (j < total) {
+      int q = 0;
+      while (s_cum[q + 1] <= j) ++q;
+      const int64_t i0 = s_w0[q] + (j - s_cum[q]) * per;
+      to[3 * j] = s;
+      to[3 * j + 1] = i0;
+      to[3 * j + 2] = min(s_w1[q], i0 + per);
+    } else {
+      to[3 * j] = -1;
+      to[3 * j + 1] = 0;
+      to[3 * j + 2] = 0;
+    }
   }
 }
 
@@ -713,14 +746,21 @@ extern "C" bls_status pp_adam(float* d_theta, float* d_m, float* d_v, const floa
   return launched() ? BLS_OK : BLS_E_HIP;
 }
 
+extern "C" bls_status pp_tile_capacity(const bls_plan* plan, int64_t* n) {
+  if (!plan || !n) return BLS_E_ARG;
+  *n = plan->tile_capacity;
+  return BLS_OK;
+}
+
 extern "C" bls_status pp_propose(const bls_plan* plan, void* ws, const float* d_logits, int32_t topk, float conf,
-                                 int64_t* d_windows, uint8_t* d_fallback, float* d_conf, bls_stream_t stream) {
+                                 int64_t* d_windows, uint8_t* d_fallback, float* d_conf, int64_t* d_tiles,
+                                 bls_stream_t stream) {
   if (!plan || !d_logits || !d_windows || !d_fallback || topk < 1 || topk > PP_MAX_WINDOWS - 2) return BLS_E_ARG;
   if (!ws_ready(plan, ws)) return BLS_E_STATE;
   if (plan->n_stars == 0) return BLS_OK;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const StarDesc* sd = reinterpret_cast<const StarDesc*>(static_cast<char*>(ws) + plan->layout.stars);
   hipLaunchKernelGGL(k_propose, dim3(plan->n_stars), dim3(64), 0, st, sd, d_logits, topk, conf, d_windows,
-                     d_fallback, d_conf);
+                     d_fallback, d_conf, d_tiles);
   return launched() ? BLS_OK : BLS_E_HIP;
 }

@@ -467,15 +467,12 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
     const int64_t* __restrict__ cw = a.cw + d.p_off;
     const int64_t* __restrict__ cs = a.cs + d.p_off;
 
-    double f_first;
-    int32_t nb_cap;
-    grid_point(d, it.i0, noverlap, f_first, nb_cap);
-    if (nb_cap > kNbLimit || nb_cap < 1) continue;  // rejected by the plan
-    // Slot stride: nb_cap bins plus room to replicate the first m_max bins after
-    // the last, so windows that wrap past bin nb-1 read contiguously.
-    const int stride_i = nb_cap + m_max;
-    const float inv_stride_i = 1.0f / static_cast<float>(stride_i);
-    const int F_act = min(kFMax, kArrElems / stride_i);
+    {
+      double f_first;
+      int32_t nb_first;
+      grid_point(d, it.i0, noverlap, f_first, nb_first);
+      if (nb_first > kNbLimit || nb_first < 1) continue;  // rejected by the plan
+    }
 
     // Points: wave w owns a contiguous block of 64 * run points per chunk; lane l
     // holds points block + 64 u + l, so a point's predecessor is in the previous
@@ -486,13 +483,19 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
     const int64_t chunk_pts = static_cast<int64_t>(run) * T;
     const double dt_last = dt[n - 1];
 
-    for (int g0 = it.i0; g0 < it.i1; g0 += F_act) {
-      const int F = min(F_act, it.i1 - g0);
-      // Per-group copies of the slot geometry: keeps the compiler from hoisting
-      // every slot's indexes out of this loop (they would stay live across the fold).
-      int stride = __builtin_amdgcn_readfirstlane(stride_i);
-      float inv_stride = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, inv_stride_i)));
-      asm volatile("" : "+s"(stride), "+s"(inv_stride));
+    for (int g0 = it.i0, F = 0; g0 < it.i1; g0 += F) {
+      // Slot geometry of this group: the fine-bin count falls with frequency, so
+      // the group's first frequency has the most bins (nb_cap); the stride holds
+      // nb_cap bins plus room to replicate the first m_max bins after the last,
+      // so windows that wrap past bin nb-1 read contiguously.  Recomputing it per
+      // group lets long ranges take more frequencies per group as nb shrinks.
+      double f_g;
+      int32_t nb_cap;
+      grid_point(d, g0, noverlap, f_g, nb_cap);
+      int stride = __builtin_amdgcn_readfirstlane(nb_cap + m_max);
+      asm volatile("" : "+s"(stride));
+      const float inv_stride = 1.0f / static_cast<float>(stride);
+      F = min(min(kFMax, kArrElems / stride), it.i1 - g0);
       if (tid < F) {
         double f;
         int32_t nb;

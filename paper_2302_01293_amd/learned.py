@@ -152,6 +152,9 @@ class LearnedSearch:
         self.windows = torch.empty((S, PP_MAX_WINDOWS, 3), dtype=torch.int64, device=dev)
         self.fallback = torch.empty(S, dtype=torch.uint8, device=dev)
         self.confidence = torch.empty(S, dtype=torch.float32, device=dev)
+        cap = ctypes.c_int64()
+        check("pp_tile_capacity", _lib.lib().pp_tile_capacity(self.fine.plan.h, ctypes.byref(cap)))
+        self.tiles = torch.empty((int(cap.value), 3), dtype=torch.int64, device=dev)
         self.logits = None
 
     def run(self, stream=None):
@@ -164,9 +167,9 @@ class LearnedSearch:
         self.logits = self.net.forward(x, lag, None, stream)
         check("pp_propose", L.pp_propose(f.plan.h, f.ws_ptr, self.logits.data_ptr(), self.topk, self.conf,
                                          self.windows.data_ptr(), self.fallback.data_ptr(),
-                                         self.confidence.data_ptr(), h))
+                                         self.confidence.data_ptr(), self.tiles.data_ptr(), h))
         c.run_search(stream)
-        f.run_search(stream, windows=self.windows.view(-1, 3))
+        f.run_search(stream, windows=self.tiles)
         check("pp_snr_windows", L.pp_snr_windows(f.plan.h, f.ws_ptr, f.sr.data_ptr(), f.best.data_ptr(),
                                                  c.plan.h, c.ws_ptr, c.sr.data_ptr(), self.windows.data_ptr(),
                                                  PP_MAX_WINDOWS, self.fallback.data_ptr(), f.result.data_ptr(),

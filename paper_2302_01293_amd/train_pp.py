@@ -1,0 +1,106 @@
+"""Train the period-proposal network on the GPU and compare the learned path with
+the plain search on held-out light curves.
+
+    python -m paper_2302_01293_amd.train_pp --n-train 8192 --n-eval 2048 \
+        --max-sectors 3 --epochs 40 --out pp_weights.npy --report pp_report.json
+
+Training light curves are the trapezoid-injection recipe of ``synth.config3``;
+labels come from the plain search on each of them (``learned.plain_labels``).
+The report gives, for the untrained and the trained network on the evaluation
+stars: recovery of the plain detections, the fraction of stars that fell back
+to the full grid, the searched fraction of the grid, and the device time of both
+paths (learned and plain) with their ratio.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def labelled(batch, chunk: int = 2048):
+    """Plain-search labels and network inputs of a batch, in chunks of stars."""
+    import torch
+    from . import learned
+    xs, lags, labels, res = [], [], [], []
+    for s0 in range(0, batch.n_stars, chunk):
+        sub = batch.subset(np.arange(s0, min(batch.n_stars, s0 + chunk)))
+        x, lag, lab, r = learned.labelled_inputs(sub)
+        xs.append(x)
+        lags.append(lag)
+        labels.append(lab)
+        res.append(r)
+        torch.cuda.synchronize()
+    return torch.cat(xs), torch.cat(lags), np.concatenate(labels), np.concatenate(res)
+
+
+def evaluate(batch, net, tag: str, conf: float = 0.9, topk: int = 8):
+    from . import learned
+    out, _, _ = learned.time_paths(batch, net, conf=conf, topk=topk)
+    log("%s: recovery %d/%d = %.4f, exact index %d, fallback %.3f, searched %.3f, plain %.1f ms, "
+        "learned %.1f ms, speed-up %.2fx" % (tag, out["recovered"], out["plain_detections"], out["recovery"],
+                                              out["exact_index"], out["fallback_fraction"],
+                                              out["searched_fraction"], out["plain_ms"], out["learned_ms"],
+                                              out["speedup"]))
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n-train", type=int, default=8192)
+    ap.add_argument("--n-eval", type=int, default=2048)
+    ap.add_argument("--max-sectors", type=int, default=3)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--conf", type=float, default=0.9)
+    ap.add_argument("--sweep", default="", help="comma-separated confidence thresholds to evaluate after training")
+    ap.add_argument("--topk", type=int, default=8)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default="")
+    ap.add_argument("--report", default="")
+    args = ap.parse_args(argv)
+
+    import torch
+    from . import learned, synth
+    assert torch.cuda.is_available(), "training runs on the GPU"
+    t0 = time.time()
+    train = synth.config3(args.n_train, start=0, max_sectors=args.max_sectors)
+    evalb = synth.config3(args.n_eval, start=args.n_train, max_sectors=args.max_sectors)
+    log("generated %d + %d light curves (%.1f s)" % (train.n_stars, evalb.n_stars, time.time() - t0))
+    t1 = time.time()
+    x, lag, labels, _ = labelled(train)
+    log("labelled by the plain search: %d periods, %d null (%.1f s)" % ((labels >= 0).sum(), (labels < 0).sum(),
+                                                                        time.time() - t1))
+    net = learned.ProposalNet(seed=args.seed)
+    before = evaluate(evalb, net, "untrained", args.conf)
+    t2 = time.time()
+    hist = learned.train(net, x, lag, labels, epochs=args.epochs, batch=args.batch, lr=args.lr, seed=args.seed,
+                         log=log)
+    torch.cuda.synchronize()
+    log("trained %d steps (%.1f s)" % (net.step, time.time() - t2))
+    after = evaluate(evalb, net, "trained", args.conf, args.topk)
+    sweep = {}
+    for c in [float(v) for v in args.sweep.split(",") if v]:
+        sweep[str(c)] = evaluate(evalb, net, "trained, conf %.3f" % c, c, args.topk)
+    rep = dict(n_train=train.n_stars, n_eval=evalb.n_stars, max_sectors=args.max_sectors, epochs=args.epochs,
+               batch=args.batch, lr=args.lr, conf=args.conf, steps=net.step, loss_first=hist[0],
+               loss_last=hist[-1], label_periods=int((labels >= 0).sum()), untrained=before, trained=after, sweep=sweep,
+               topk=args.topk)
+    if args.out:
+        np.save(args.out, net.params_host())
+    if args.report:
+        with open(args.report, "w") as fh:
+            json.dump(rep, fh, indent=1)
+    print(json.dumps(rep), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -180,10 +180,29 @@ def test_propose_parity(oracle):
     win = torch.empty((S, _lib.PP_MAX_WINDOWS, 3), dtype=torch.int64, device="cuda")
     fb = torch.empty(S, dtype=torch.uint8, device="cuda")
     cf = torch.empty(S, dtype=torch.float32, device="cuda")
+    import ctypes
+    cap = ctypes.c_int64()
+    _lib.check("pp_tile_capacity", _lib.lib().pp_tile_capacity(ds.plan.h, ctypes.byref(cap)))
+    tiles = torch.empty((int(cap.value), 3), dtype=torch.int64, device="cuda")
     _lib.check("pp_propose", _lib.lib().pp_propose(ds.plan.h, ds.ws_ptr, zd.data_ptr(), 8, 0.9, win.data_ptr(),
-                                                   fb.data_ptr(), cf.data_ptr(), 0))
+                                                   fb.data_ptr(), cf.data_ptr(), tiles.data_ptr(), 0))
     torch.cuda.synchronize()
     wg, fg, cg = win.cpu().numpy(), fb.cpu().numpy(), cf.cpu().numpy()
+    tg = tiles.cpu().numpy()
+    # the tiled list covers exactly the windows of every star, in pieces of at most
+    # the star's tile size
+    for s in range(S):
+        cov_w = set()
+        for r in wg[s]:
+            if r[0] == s:
+                cov_w.update(range(r[1], r[2]))
+        rows = tg[tg[:, 0] == s]
+        cov_t = []
+        for r in rows:
+            cov_t.extend(range(r[1], r[2]))
+        assert set(cov_t) == cov_w, s
+        assert len(cov_t) <= len(cov_w) + _lib.PP_MAX_WINDOWS   # windows meet at most at one index
+        assert np.all(rows[:, 2] > rows[:, 1])
     for s in range(S):
         f, bd = _oracle_grid(oracle, b, s)
         ro, co, fo = P.propose(z[s].astype(np.float64), bd.pmin, bd.pmax, bd.umin, bd.A, len(f))
