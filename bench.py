@@ -61,14 +61,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_workload(name: str):
+def make_workload(name: str, n_stars: int = 0):
     from paper_2302_01293_amd import synth
     if name == "cfg0":
         return synth.config0(), "1 star, 27.4 d at 30-min cadence, P 0.5-13.7 d, plain FP64"
     if name == "cfg1":
         return synth.config1(), "4096 stars x 1 sector at 200 s (11,405 pts), Pmin a=2R*, plain FP64"
     if name == "cfg2":
-        return synth.config2(), "16384 stars, 1-13 sectors (ragged), plain FP64"
+        n = n_stars or 16384
+        return synth.config2(n), "%d stars, 1-13 sectors at 200 s (uneven, missing sectors)" % n
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -108,6 +109,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg1")
     ap.add_argument("--stars", type=int, default=0, help="use only the first N stars of the workload")
+    ap.add_argument("--precision", type=int, default=0,
+                    help="0: exact int64 bin sums (plain FP64 path); 1: packed reduced-precision sums")
     ap.add_argument("--cpu-sample", type=int, default=768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
@@ -138,12 +141,15 @@ def main():
                                                                   args.copy_calibration_mib))
         del src, dst
     log("generating workload", args.workload)
-    batch, desc = make_workload(args.workload)
+    batch, desc = make_workload(args.workload, args.stars if args.workload == "cfg2" else 0)
     if args.stars and args.stars < batch.n_stars:
         batch = batch.subset(np.arange(args.stars))
         desc += " (first %d stars)" % args.stars
     log("stars", batch.n_stars, "points", batch.n_points)
-    ds = DeviceSearch.from_batch(batch)
+    from paper_2302_01293_amd import _lib
+    ds = DeviceSearch.from_batch(batch, _lib.default_params(precision=args.precision))
+    if args.precision:
+        desc += ", packed reduced-precision sums"
     nfs = np.diff(ds.plan.freq_offsets)
     npts = np.diff(batch.offsets)
     cells = float(np.sum(nfs.astype(np.float64) * npts))
@@ -201,7 +207,7 @@ def main():
         "kernel_ms": {"prepare": prep, "search": srch, "snr": snr},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic(args.workload) if not args.stars else None,
+                     "traffic": measured_traffic(args.workload) if not (args.stars or args.precision) else None,
                      "kernel": "k_search (fold + boundary accumulation + scan)"},
     }
     if not args.no_learned:

@@ -68,8 +68,11 @@ typedef struct bls_params {
   int32_t dip_only;    /* 0: windows of either sign count (Kovacs s^2); 1: s < 0 only */
   int32_t mad_of_raw;  /* 0: sigma from the MAD of the detrended SR (default);
                           1: from the MAD of raw SR */
-  int32_t precision;   /* 0: FP64 phase and FP64-exact sums (plain path);
-                          1: FP64 phase, FP32 compensated bin sums (fast path) */
+  int32_t precision;   /* 0: FP64 phase, exact int64 fixed-point bin sums (plain path);
+                          1: FP64 phase, weights (2^-27) and weighted residuals packed
+                          into one 64-bit fixed-point sum per bin: half the LDS atomics,
+                          SR within ~1e-5 relative of the exact sums (reduced precision;
+                          best-period indices can differ at near-ties) */
   double a_min_rstar;  /* minimum a/R*: 2 (Sectors 61+) or 3 (Sectors 59-60) */
   double sector_days;  /* gap length that splits continuous stretches (27.4) */
   int64_t tile_cells;  /* target points x frequencies per work item; 0 = library default
@@ -187,6 +190,10 @@ void bls_plan_destroy(bls_plan* plan);
 
 /* Static text naming a status code. */
 const char* bls_status_string(bls_status s);
+
+/* HIP error code (hipError_t value) of the last HIP call that failed inside the
+ * library on the calling thread, behind a BLS_E_HIP return; 0 if none. */
+int32_t bls_last_hip_error(void);
 
 /* Compiled limits: out[0] = maximum fine bins per frequency, out[1] = maximum
  * duration-ladder length, out[2] = maximum points per star. */

@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "BLS_OK", -1: "BLS_E_ARG", -2: "BLS_E_INPUT", -3: "BLS_E_EMPT
 
 EXPORTS = ("bls_default_params", "bls_plan_create", "bls_plan_query", "bls_plan_star_info",
            "bls_plan_frequencies", "bls_plan_durations", "bls_plan_upload", "bls_prepare", "bls_search_batch",
-           "bls_snr", "bls_plan_destroy", "bls_status_string", "bls_limits",
+           "bls_snr", "bls_plan_destroy", "bls_status_string", "bls_limits", "bls_last_hip_error",
            # learned period proposal (include/mi355pp.h)
            "pp_act_bytes", "pp_resample", "pp_forward", "pp_backward", "pp_adam", "pp_propose",
            "pp_tile_capacity", "pp_snr_windows")
@@ -61,6 +61,8 @@ class BlsError(RuntimeError):
         msg = "%s failed: %s (%d)" % (where, STATUS_NAMES.get(code, "?"), code)
         if star is not None and star >= 0:
             msg += " at star %d" % star
+        if code == -5 and _lib is not None:
+            msg += " (hipError %d)" % int(_lib.bls_last_hip_error())
         super().__init__(msg)
         self.code = code
         self.star = star
@@ -73,6 +75,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libmi355bls.so not built: run `python -m paper_2302_01293_amd.build` "
                               "(or __graft_entry__.build())")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64 (same soname
+        # as the system one the library links).  Loading torch first makes the
+        # library bind to torch's copy; loading the library first would bring in a
+        # second runtime, and then one of the two finds no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.bls_default_params.restype = i32
@@ -102,6 +112,8 @@ def lib():
         L.bls_status_string.argtypes = [i32]
         L.bls_limits.restype = i32
         L.bls_limits.argtypes = [vp]
+        L.bls_last_hip_error.restype = i32
+        L.bls_last_hip_error.argtypes = []
         f32 = ctypes.c_float
         L.pp_act_bytes.restype = i32
         L.pp_act_bytes.argtypes = [i32, ctypes.POINTER(i64)]

@@ -125,6 +125,7 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
   uint32_t mask = 0;
   for (int32_t m : ladder) mask |= 1u << (m - 1);
   plan->consts.m_mask = mask;
+  plan->consts.packed = p->precision == 1 ? 1 : 0;
   try {
     plan->stars.resize(n_stars);
     plan->freq_offsets.assign(n_stars + 1, 0);
@@ -355,3 +356,15 @@ extern "C" bls_status bls_limits(int64_t* o) {
   o[2] = kMaxPoints;
   return BLS_OK;
 }
+
+namespace mi355bls {
+namespace {
+thread_local int g_last_hip_error = 0;
+}
+bls_status hip_failed(int hip_error_code) {
+  g_last_hip_error = hip_error_code;
+  return BLS_E_HIP;
+}
+}  // namespace mi355bls
+
+extern "C" int32_t bls_last_hip_error(void) { return mi355bls::g_last_hip_error; }

@@ -53,11 +53,19 @@ static_assert(sizeof(StarDesc) == 128, "StarDesc layout");
 
 // Per-star values written by the preparation kernel.
 struct StarRt {
-  int64_t cw_total;  // sum of fixed-point weights (units of 2^-62)
-  int64_t cs_total;  // sum of fixed-point weighted residuals (units of s_scale)
+  int64_t cw_total;  // sum of fixed-point weights (units of 2^-62); packed: the packed total
+  int64_t cs_total;  // sum of fixed-point weighted residuals (units of s_scale); packed: 0
   double s_scale;    // 2^-e: value of one unit of the residual fixed point
   double pad;
 };
+
+// Packed fixed point (precision 1): w~ in units of 2^-27 in the high 28 bits and
+// w~ x in units of s_scale in the low 36 bits (two's complement) of one 64-bit
+// integer, summed modulo 2^64.  A bin's total holds at most 2^27 + n/2 < 2^28
+// weight units and |residual| < 2^35 units, so both fields decode exactly; bin
+// weights are then divided by the star's quantised total.
+constexpr int kPackShift = 36;
+constexpr int kPackWBits = 27;
 
 // A work item: frequencies [i0, i1) of one star.
 struct WorkItem {
@@ -71,14 +79,25 @@ struct Consts {
   int32_t mad_of_raw;
   int32_t m_max;       // longest duration in bins
   uint32_t m_mask;     // bit (m-1) set for every duration m of the ladder
-  int32_t pad;
+  int32_t packed;      // 1: weights and residuals share one int64 per point (precision 1)
 };
 
 struct Layout {  // byte offsets inside the device workspace
   int64_t stars, rt, items, gaps, dt, cw, cs, rho, counter, total;
 };
 
+// Records the HIP error code of a failed HIP call (per thread) and returns
+// BLS_E_HIP; bls_last_hip_error() reads it back.
+bls_status hip_failed(int hip_error_code);
+
 }  // namespace mi355bls
+
+// Return from an entry point with BLS_E_HIP (recording the code) if a HIP call fails.
+#define BLS_HIP_TRY(call)                                                          \
+  do {                                                                             \
+    const int bls_hip_e_ = static_cast<int>(call);                                 \
+    if (bls_hip_e_ != 0) return mi355bls::hip_failed(bls_hip_e_);                 \
+  } while (0)
 
 struct bls_plan {
   bls_params params;

@@ -688,7 +688,6 @@ using namespace mi355pp;
 
 namespace {
 bool ws_ready(const bls_plan* plan, const void* ws) { return plan && ws && plan->uploaded_to == ws; }
-bool launched() { return hipGetLastError() == hipSuccess; }
 }  // namespace
 
 extern "C" bls_status pp_act_bytes(int32_t batch, int64_t* bytes) {
@@ -705,7 +704,8 @@ extern "C" bls_status pp_resample(const bls_plan* plan, void* ws, const double* 
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const StarDesc* sd = reinterpret_cast<const StarDesc*>(static_cast<char*>(ws) + plan->layout.stars);
   hipLaunchKernelGGL(k_resample, dim3(plan->n_stars), dim3(1024), 0, st, sd, d_t, d_y, d_w, d_x, d_lag);
-  return launched() ? BLS_OK : BLS_E_HIP;
+  BLS_HIP_TRY(hipGetLastError());
+  return BLS_OK;
 }
 
 extern "C" bls_status pp_forward(const float* d_theta, const uint16_t* d_x, const double* d_lag, int32_t batch,
@@ -715,7 +715,8 @@ extern "C" bls_status pp_forward(const float* d_theta, const uint16_t* d_x, cons
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(k_forward, dim3(batch), dim3(256), kFwdLds, st, d_theta, d_x, d_lag, d_logits,
                      static_cast<unsigned char*>(d_act));
-  return launched() ? BLS_OK : BLS_E_HIP;
+  BLS_HIP_TRY(hipGetLastError());
+  return BLS_OK;
 }
 
 extern "C" bls_status pp_backward(const float* d_theta, const uint16_t* d_x, const double* d_lag,
@@ -728,10 +729,11 @@ extern "C" bls_status pp_backward(const float* d_theta, const uint16_t* d_x, con
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(k_backward, dim3(batch), dim3(256), kBwdLds, st, d_theta, d_x, d_lag, d_target, d_logits,
                      static_cast<const unsigned char*>(d_act), d_gpart, d_lpart);
-  if (!launched()) return BLS_E_HIP;
+  BLS_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_reduce, dim3((kNParam + 255) / 256), dim3(256), 0, st, d_gpart, d_lpart, batch, d_grad,
                      d_loss);
-  return launched() ? BLS_OK : BLS_E_HIP;
+  BLS_HIP_TRY(hipGetLastError());
+  return BLS_OK;
 }
 
 extern "C" bls_status pp_adam(float* d_theta, float* d_m, float* d_v, const float* d_grad, int32_t step, float lr,
@@ -743,7 +745,8 @@ extern "C" bls_status pp_adam(float* d_theta, float* d_m, float* d_v, const floa
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipLaunchKernelGGL(k_adam, dim3((kNParam + 255) / 256), dim3(256), 0, st, d_theta, d_m, d_v, d_grad, lr,
                      static_cast<float>(b1), static_cast<float>(b2), 1e-8f, c1, c2);
-  return launched() ? BLS_OK : BLS_E_HIP;
+  BLS_HIP_TRY(hipGetLastError());
+  return BLS_OK;
 }
 
 extern "C" bls_status pp_tile_capacity(const bls_plan* plan, int64_t* n) {
@@ -762,5 +765,6 @@ extern "C" bls_status pp_propose(const bls_plan* plan, void* ws, const float* d_
   const StarDesc* sd = reinterpret_cast<const StarDesc*>(static_cast<char*>(ws) + plan->layout.stars);
   hipLaunchKernelGGL(k_propose, dim3(plan->n_stars), dim3(64), 0, st, sd, d_logits, topk, conf, d_windows,
                      d_fallback, d_conf, d_tiles);
-  return launched() ? BLS_OK : BLS_E_HIP;
+  BLS_HIP_TRY(hipGetLastError());
+  return BLS_OK;
 }

@@ -80,13 +80,15 @@ __device__ T block_sum(T v, T* scratch) {
   return r;
 }
 
-// Exclusive block scan of one int64 per thread; returns the total through *total.
-__device__ int64_t block_exscan(int64_t v, int64_t* scratch, int64_t* total) {
+// Exclusive block scan of one integer per thread (unsigned: wraps modulo 2^64);
+// returns the total through *total.
+template <typename I>
+__device__ I block_exscan(I v, I* scratch, I* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int64_t x = v;
+  I x = v;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    const int64_t y = __shfl_up(x, o, 64);
+    const I y = __shfl_up(x, o, 64);
     if (lane >= o) x += y;
   }
   __syncthreads();
@@ -94,16 +96,16 @@ __device__ int64_t block_exscan(int64_t v, int64_t* scratch, int64_t* total) {
   __syncthreads();
   if (wave == 0) {
     const int nw = blockDim.x >> 6;
-    int64_t s = lane < nw ? scratch[lane] : 0;
+    I s = lane < nw ? scratch[lane] : I(0);
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-      const int64_t y = __shfl_up(s, o, 64);
+      const I y = __shfl_up(s, o, 64);
       if (lane >= o) s += y;
     }
     if (lane < nw) scratch[lane] = s;  // inclusive per wave
   }
   __syncthreads();
-  const int64_t wave_off = wave > 0 ? scratch[wave - 1] : 0;
+  const I wave_off = wave > 0 ? scratch[wave - 1] : I(0);
   *total = scratch[(blockDim.x >> 6) - 1];
   __syncthreads();
   return wave_off + x - v;
@@ -160,17 +162,21 @@ __device__ double block_csum(CSum v, CSum* scratch) {
 // ----------------------------------------------------------------------------
 // Preparation: one workgroup per star.
 //   W = sum w, wt = w / W, ybar = sum wt y (both compensated), x = y - ybar,
-//   a = sum |wt x|.  Fixed point: Wq = rint(wt 2^62), Sq = rint(wt x 2^e) with
-//   2^e a <= 2^62, so every window sum fits in int64.  Outputs dt = t - t0 and the
-//   exclusive prefix sums CW, CS.
+//   a = sum |wt x|.  Fixed point (precision 0): Wq = rint(wt 2^62), Sq = rint(wt x
+//   2^es) with 2^-es a <= 2^62, so every window sum fits in int64; outputs the
+//   exclusive prefix sums CW, CS.  Packed (precision 1): Wq = rint(wt 2^27) in the
+//   high 28 bits and Sq = rint(wt x 2^es) with a 2^es <= 2^34 in the low 36 bits of
+//   one integer, one prefix sum modulo 2^64 in CW.  Also dt = t - t0.  The scans run
+//   tile by tile over the star (coalesced), carrying the running total.
 // ----------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) k_prepare(const StarDesc* __restrict__ stars, StarRt* __restrict__ rt,
                                                       const double* __restrict__ t, const double* __restrict__ y,
                                                       const double* __restrict__ w, double* __restrict__ dt_out,
-                                                      int64_t* __restrict__ cw_out, int64_t* __restrict__ cs_out) {
+                                                      int64_t* __restrict__ cw_out, int64_t* __restrict__ cs_out,
+                                                      int32_t packed) {
   __shared__ CSum sc[16];
   __shared__ double sd[16];
-  __shared__ int64_t si[32];
+  __shared__ unsigned long long si[32];
   const StarDesc d = stars[blockIdx.x];
   const int64_t n = d.n, off = d.p_off;
   const int tid = threadIdx.x, T = blockDim.x;
@@ -193,32 +199,39 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const StarDesc* __restrict
   if (absum > 0.0) {
     frexp(absum, &e);  // absum < 2^e
   }
-  const int es = 62 - e;
+  const int es = (packed ? 34 : 62) - e;
 
-  // Contiguous runs per thread for the scans.
-  const int64_t run = (n + T - 1) / T;
-  const int64_t a = min<int64_t>(n, tid * run), b = min<int64_t>(n, a + run);
-  int64_t lw = 0, ls = 0;
-  for (int64_t i = a; i < b; ++i) {
-    const double wt = (w ? w[off + i] : 1.0) / W;
-    lw += static_cast<int64_t>(rint(ldexp(wt, 62)));
-    ls += static_cast<int64_t>(rint(ldexp(wt * (y[off + i] - ybar), es)));
-  }
-  int64_t tw, ts;
-  int64_t pw = block_exscan(lw, si, &tw);
-  int64_t ps = block_exscan(ls, si, &ts);
-  for (int64_t i = a; i < b; ++i) {
-    const double wt = (w ? w[off + i] : 1.0) / W;
-    cw_out[off + i] = pw;
-    cs_out[off + i] = ps;
-    pw += static_cast<int64_t>(rint(ldexp(wt, 62)));
-    ps += static_cast<int64_t>(rint(ldexp(wt * (y[off + i] - ybar), es)));
-    dt_out[off + i] = t[off + i] - d.t0;
+  unsigned long long carry_w = 0, carry_s = 0;
+  for (int64_t base = 0; base < n; base += T) {
+    const int64_t i = base + tid;
+    unsigned long long qw = 0, qs = 0;
+    if (i < n) {
+      const double wt = (w ? w[off + i] : 1.0) / W;
+      const long long sq = static_cast<long long>(rint(ldexp(wt * (y[off + i] - ybar), es)));
+      if (packed) {
+        qw = (static_cast<unsigned long long>(rint(ldexp(wt, kPackWBits))) << kPackShift) +
+             static_cast<unsigned long long>(sq);
+      } else {
+        qw = static_cast<unsigned long long>(static_cast<long long>(rint(ldexp(wt, 62))));
+        qs = static_cast<unsigned long long>(sq);
+      }
+    }
+    unsigned long long tw, ts = 0;
+    const unsigned long long pw = block_exscan<unsigned long long>(qw, si, &tw);
+    unsigned long long ps = 0;
+    if (!packed) ps = block_exscan<unsigned long long>(qs, si, &ts);
+    if (i < n) {
+      cw_out[off + i] = static_cast<int64_t>(carry_w + pw);
+      if (!packed) cs_out[off + i] = static_cast<int64_t>(carry_s + ps);
+      dt_out[off + i] = t[off + i] - d.t0;
+    }
+    carry_w += tw;
+    carry_s += ts;
   }
   if (tid == 0) {
     StarRt r;
-    r.cw_total = tw;
-    r.cs_total = ts;
+    r.cw_total = static_cast<int64_t>(carry_w);
+    r.cs_total = static_cast<int64_t>(carry_s);
     r.s_scale = ldexp(1.0, -es);
     r.pad = 0.0;
     rt[blockIdx.x] = r;
@@ -304,7 +317,7 @@ __device__ __forceinline__ void slot_of(int idx, int stride, float inv_stride, i
 // One pass of the fold over the wave's block for frequencies k0 and, when TWO,
 // k0 + 1: a point whose bin differs from its predecessor's is a boundary and adds
 // its prefix values into G of its bin.
-template <bool TWO>
+template <bool TWO, bool PACKED>
 __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k0, const GroupLds* g,
                                           const double (&dtr)[kUMax], const long long (&cwr)[kUMax],
                                           const long long (&csr)[kUMax], double dt_before, int run) {
@@ -373,7 +386,7 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
       if (ba[v] != pa) {
         const uint32_t o = ga + 8u * static_cast<uint32_t>(ba[v]);
         lds_add64(smem, o, cwr[u]);
-        lds_add64(smem, o + kArrBytes, csr[u]);
+        if (!PACKED) lds_add64(smem, o + kArrBytes, csr[u]);
       }
       if (TWO) {
         const int32_t lb = (v == 0 && u0 == 0) ? prev_b : __builtin_amdgcn_mov_dpp(v == 0 ? prev_b : bb[v - 1], 0x13C, 0xf, 0xf, false);
@@ -381,7 +394,7 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
         if (bb[v] != pb) {
           const uint32_t o = gb + 8u * static_cast<uint32_t>(bb[v]);
           lds_add64(smem, o, cwr[u]);
-          lds_add64(smem, o + kArrBytes, csr[u]);
+          if (!PACKED) lds_add64(smem, o + kArrBytes, csr[u]);
         }
       }
     }
@@ -406,6 +419,25 @@ __global__ void k_reset(unsigned int* next) {
   if (threadIdx.x < kXcds) next[threadIdx.x * kCounterStride] = 0u;
 }
 
+// Packed total -> (weight units, residual units).
+__device__ __forceinline__ void unpack_units(unsigned long long h, unsigned long long& wsum, long long& ssum) {
+  ssum = static_cast<long long>(h << (64 - kPackShift)) >> (64 - kPackShift);
+  wsum = (h - static_cast<unsigned long long>(ssum)) >> kPackShift;
+}
+
+// Packed bin total -> (weight fraction, residual).  The weight is divided by the
+// star's quantised total rather than taken in units of 2^-27: with equal weights
+// every point rounds the same way, and only the ratio stays exact.
+__device__ __forceinline__ void unpack(unsigned long long h, double s_scale, double w_unit, double& vw,
+                                       double& vs) {
+  unsigned long long wsum;
+  long long ssum;
+  unpack_units(h, wsum, ssum);
+  vw = static_cast<double>(wsum) * w_unit;
+  vs = static_cast<double>(ssum) * s_scale;
+}
+
+template <bool PACKED>
 __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   long long* GW = reinterpret_cast<long long*>(smem);
@@ -462,6 +494,13 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
     if (it.i1 <= it.i0) continue;
     const StarDesc d = a.stars[it.star];
     const StarRt rt = a.rt[it.star];
+    double w_unit = 0.0;  // packed: 1 / quantised total weight
+    if (PACKED) {
+      unsigned long long wt_units;
+      long long st_units;
+      unpack_units(static_cast<unsigned long long>(rt.cw_total), wt_units, st_units);
+      w_unit = 1.0 / static_cast<double>(wt_units);
+    }
     const int64_t n = d.n;
     const double* __restrict__ dt = a.dt + d.p_off;
     const int64_t* __restrict__ cw = a.cw + d.p_off;
@@ -527,14 +566,14 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
           const int64_t q = min<int64_t>(wbase + u * 64 + lane, wend - 1);
           dtr[u] = dt[q];
           cwr[u] = cw[q];
-          csr[u] = cs[q];
+          csr[u] = PACKED ? 0 : cs[q];
         }
         const double dt_before = dt[wbase > 0 ? wbase - 1 : 0];
         for (int k0 = 0; k0 < F; k0 += 2) {
           if (k0 + 1 < F)
-            fold_pass<true>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run);
+            fold_pass<true, PACKED>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run);
           else
-            fold_pass<false>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run);
+            fold_pass<false, PACKED>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run);
         }
       }
       __syncthreads();
@@ -552,24 +591,30 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
         const int mrep = min(m_max, nb - 1);
         long long* gw = GW + k * stride;
         long long* gs = GS + k * stride;
-        const long long g0w = gw[0], g0s = gs[0];
+        const long long g0w = gw[0], g0s = PACKED ? 0 : gs[0];
         for (int b0 = 0; b0 < nb; b0 += 64) {
           const int b = b0 + lane;
           if (b < nb) {
             const long long nw = b + 1 < nb ? gw[b + 1] : g0w;
-            const long long ns = b + 1 < nb ? gs[b + 1] : g0s;
+            const long long ns = PACKED ? 0 : (b + 1 < nb ? gs[b + 1] : g0s);
             unsigned long long dw = static_cast<unsigned long long>(nw) - static_cast<unsigned long long>(gw[b]);
-            unsigned long long ds = static_cast<unsigned long long>(ns) - static_cast<unsigned long long>(gs[b]);
+            unsigned long long ds = PACKED ? 0ull
+                                           : static_cast<unsigned long long>(ns) - static_cast<unsigned long long>(gs[b]);
             if (b == bl) {
               dw += static_cast<unsigned long long>(rt.cw_total);
               ds += static_cast<unsigned long long>(rt.cs_total);
             }
             if (gaps) {
               gw[b] = static_cast<long long>(dw);
-              gs[b] = static_cast<long long>(ds);
+              if (!PACKED) gs[b] = static_cast<long long>(ds);
             } else {
-              const double vw = static_cast<double>(static_cast<long long>(dw)) * kW62;
-              const double vs = static_cast<double>(static_cast<long long>(ds)) * rt.s_scale;
+              double vw, vs;
+              if (PACKED) {
+                unpack(dw, rt.s_scale, w_unit, vw, vs);
+              } else {
+                vw = static_cast<double>(static_cast<long long>(dw)) * kW62;
+                vs = static_cast<double>(static_cast<long long>(ds)) * rt.s_scale;
+              }
               double* hw = reinterpret_cast<double*>(gw);
               double* hs = reinterpret_cast<double*>(gs);
               hw[b] = vw;
@@ -605,11 +650,15 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
           if (steps > 1) {
             const int32_t bm1 = bu == 0 ? nb - 1 : bu - 1;
             const uint32_t kb = static_cast<uint32_t>(k * stride);
-            const long long ew = cw[q], es = cs[q];
+            const long long ew = cw[q];
             atomicAdd(reinterpret_cast<unsigned long long*>(&GW[kb + bq]), static_cast<unsigned long long>(ew));
-            atomicAdd(reinterpret_cast<unsigned long long*>(&GS[kb + bq]), static_cast<unsigned long long>(es));
             atomicAdd(reinterpret_cast<unsigned long long*>(&GW[kb + bm1]), 0ull - static_cast<unsigned long long>(ew));
-            atomicAdd(reinterpret_cast<unsigned long long*>(&GS[kb + bm1]), 0ull - static_cast<unsigned long long>(es));
+            if (!PACKED) {
+              const long long es = cs[q];
+              atomicAdd(reinterpret_cast<unsigned long long*>(&GS[kb + bq]), static_cast<unsigned long long>(es));
+              atomicAdd(reinterpret_cast<unsigned long long*>(&GS[kb + bm1]),
+                        0ull - static_cast<unsigned long long>(es));
+            }
           }
         }
         __syncthreads();
@@ -619,8 +668,13 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
           slot_of(idx, stride, inv_stride, k, b);
           const int32_t nb = g->nb[k];
           if (b < nb) {
-            const double vw = static_cast<double>(GW[idx]) * kW62;
-            const double vs = static_cast<double>(GS[idx]) * rt.s_scale;
+            double vw, vs;
+            if (PACKED) {
+              unpack(static_cast<unsigned long long>(GW[idx]), rt.s_scale, w_unit, vw, vs);
+            } else {
+              vw = static_cast<double>(GW[idx]) * kW62;
+              vs = static_cast<double>(GS[idx]) * rt.s_scale;
+            }
             HW[idx] = vw;
             HS[idx] = vs;
             if (b < min(m_max, nb - 1)) {
@@ -746,17 +800,14 @@ extern "C" bls_status bls_plan_upload(bls_plan* plan, void* ws, int64_t bytes, b
   if (bytes < plan->layout.total) return BLS_E_STATE;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
-  if (hipMemcpyAsync(base + plan->layout.stars, plan->stars.data(), sizeof(StarDesc) * plan->stars.size(),
-                     hipMemcpyHostToDevice, st) != hipSuccess)
-    return BLS_E_HIP;
-  if (!plan->items.empty() &&
-      hipMemcpyAsync(base + plan->layout.items, plan->items.data(), sizeof(WorkItem) * plan->items.size(),
-                     hipMemcpyHostToDevice, st) != hipSuccess)
-    return BLS_E_HIP;
-  if (!plan->gaps.empty() &&
-      hipMemcpyAsync(base + plan->layout.gaps, plan->gaps.data(), sizeof(int32_t) * plan->gaps.size(),
-                     hipMemcpyHostToDevice, st) != hipSuccess)
-    return BLS_E_HIP;
+  BLS_HIP_TRY(hipMemcpyAsync(base + plan->layout.stars, plan->stars.data(),
+                             sizeof(StarDesc) * plan->stars.size(), hipMemcpyHostToDevice, st));
+  if (!plan->items.empty())
+    BLS_HIP_TRY(hipMemcpyAsync(base + plan->layout.items, plan->items.data(),
+                               sizeof(WorkItem) * plan->items.size(), hipMemcpyHostToDevice, st));
+  if (!plan->gaps.empty())
+    BLS_HIP_TRY(hipMemcpyAsync(base + plan->layout.gaps, plan->gaps.data(),
+                               sizeof(int32_t) * plan->gaps.size(), hipMemcpyHostToDevice, st));
   plan->uploaded_to = ws;
   return BLS_OK;
 }
@@ -771,8 +822,8 @@ extern "C" bls_status bls_prepare(bls_plan* plan, void* ws, const double* d_t, c
   hipLaunchKernelGGL(k_prepare, dim3(plan->n_stars), dim3(kThreads), 0, st,
                      reinterpret_cast<const StarDesc*>(base + L.stars), reinterpret_cast<StarRt*>(base + L.rt),
                      d_t, d_y, d_w, reinterpret_cast<double*>(base + L.dt), reinterpret_cast<int64_t*>(base + L.cw),
-                     reinterpret_cast<int64_t*>(base + L.cs));
-  if (hipGetLastError() != hipSuccess) return BLS_E_HIP;
+                     reinterpret_cast<int64_t*>(base + L.cs), plan->consts.packed);
+  BLS_HIP_TRY(hipGetLastError());
   return BLS_OK;
 }
 
@@ -803,14 +854,17 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
   a.n_items = static_cast<int32_t>(n_items);
   a.n_stars = plan->n_stars;
   int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-    return BLS_E_HIP;
+  BLS_HIP_TRY(hipGetDevice(&dev));
+  BLS_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (cus < 1) return BLS_E_HIP;
   // Persistent grid: two workgroups per CU pull items until the counter passes the end.
   const int64_t grid = std::min<int64_t>(n_items, 2 * static_cast<int64_t>(cus));
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);  // 8 counters
-  if (hipGetLastError() != hipSuccess) return BLS_E_HIP;
-  hipLaunchKernelGGL(k_search, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds, st, a);
-  if (hipGetLastError() != hipSuccess) return BLS_E_HIP;
+  BLS_HIP_TRY(hipGetLastError());
+  if (plan->consts.packed)
+    hipLaunchKernelGGL(k_search<true>, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds, st, a);
+  else
+    hipLaunchKernelGGL(k_search<false>, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds, st, a);
+  BLS_HIP_TRY(hipGetLastError());
   return BLS_OK;
 }

@@ -241,7 +241,7 @@ extern "C" bls_status bls_snr(bls_plan* plan, void* ws, const double* d_sr, cons
   hipLaunchKernelGGL(k_snr, dim3(plan->n_stars), dim3(kThreads), 0, st,
                      reinterpret_cast<const StarDesc*>(base + L.stars), d_sr, d_best, d_snr,
                      reinterpret_cast<double*>(base + L.rho), d_result, plan->consts);
-  if (hipGetLastError() != hipSuccess) return BLS_E_HIP;
+  BLS_HIP_TRY(hipGetLastError());
   return BLS_OK;
 }
 
@@ -261,6 +261,6 @@ extern "C" bls_status pp_snr_windows(const bls_plan* fine, void* fine_ws, const 
                      reinterpret_cast<double*>(fb + fine->layout.rho), d_coarse_sr,
                      reinterpret_cast<double*>(cb + coarse->layout.rho), d_windows, windows_per_star, d_fallback,
                      d_result, fine->consts);
-  if (hipGetLastError() != hipSuccess) return BLS_E_HIP;
+  BLS_HIP_TRY(hipGetLastError());
   return BLS_OK;
 }
