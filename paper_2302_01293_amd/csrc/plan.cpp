@@ -205,7 +205,8 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
     if (!(steps >= 0.0) || steps > 2.0e9) return fail(steps >= 0.0 ? BLS_E_UNSUPPORTED : BLS_E_EMPTY_GRID);
     d.nf = static_cast<int64_t>(steps) + 1;
     d.nb0 = nbins_at(d, 0, p->noverlap);
-    if (d.nb0 > kNbLimit || d.nb0 < 1) return fail(BLS_E_UNSUPPORTED);
+    if (d.nb0 > kNbWide || d.nb0 < 1) return fail(BLS_E_UNSUPPORTED);
+    if (d.nb0 > kNbLimit) plan->has_wide = true;
     const int32_t sturges =
         static_cast<int32_t>(std::floor(1.0 + 3.322 * std::log10(static_cast<double>(d.nf)) + 0.5));
     d.sturges = std::max(1, std::min(sturges, kMaxSturges));
@@ -351,7 +352,7 @@ extern "C" const char* bls_status_string(bls_status s) {
 
 extern "C" bls_status bls_limits(int64_t* o) {
   if (!o) return BLS_E_ARG;
-  o[0] = kNbLimit;
+  o[0] = kNbWide;
   o[1] = kMCap;
   o[2] = kMaxPoints;
   return BLS_OK;

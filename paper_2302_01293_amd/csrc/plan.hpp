@@ -21,8 +21,11 @@ constexpr int kSearchThreads = 512;   // threads per search workgroup; two workg
                                       // (4 waves per SIMD, up to 128 registers per lane)
 constexpr int kUMax = 12;             // register-resident points per search thread
 constexpr int kGBytes = 64 * 1024;    // LDS bytes for the per-frequency accumulators
-constexpr int kNbLimit = kGBytes / 16 - 32;  // largest fine-bin count: 16 B per bin, plus
-                                              // the replicated wrap bins
+constexpr int kNbLimit = kGBytes / 16 - 32;  // largest fine-bin count searched in one pass:
+                                              // 16 B per bin, plus the replicated wrap bins
+constexpr int kNbWide = (1 << 20) - 1;       // largest fine-bin count (window start bins
+                                              // are 20-bit fields); beyond kNbLimit a
+                                              // frequency is searched in passes over bin ranges
 constexpr int kFMax = 32;             // most frequencies processed together
 constexpr int kMCap = 32;             // longest duration (in fine bins)
 constexpr int64_t kMaxPoints = int64_t(1) << 30;
@@ -109,6 +112,7 @@ struct bls_plan {
   std::vector<int32_t> gaps;  // per star (CSR by StarDesc::g_off): point indices n >= 1
   std::vector<int64_t> freq_offsets;
   int64_t tile_capacity = 0;  // slots of a tiled window list: per star, its tiles + 16
+  bool has_wide = false;       // some frequency has more fine bins than one LDS pass holds
   std::vector<int32_t> durations;
   mi355bls::Consts consts{};
   mi355bls::Layout layout{};

@@ -437,6 +437,313 @@ __device__ __forceinline__ void unpack(unsigned long long h, double s_scale, dou
   vs = static_cast<double>(ssum) * s_scale;
 }
 
+// Next work item of this workgroup (the same for all its threads), or false when
+// every queue is empty.  `queue` and `probes` are thread 0's state.
+__device__ bool next_item(const SearchArgs& a, GroupLds* g, int& queue, int& probes, WorkItem& it) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    int32_t item = -1;
+    while (probes < kXcds) {
+      const unsigned t = atomicAdd(&a.next[queue * kCounterStride], 1u);
+      const int64_t chunk = static_cast<int64_t>(t / kQueueChunk) * kXcds + queue;
+      const int64_t cand = chunk * kQueueChunk + t % kQueueChunk;
+      if (cand < a.n_items) {
+        item = static_cast<int32_t>(cand);
+        break;
+      }
+      queue = (queue + 1) % kXcds;
+      ++probes;
+    }
+    g->item[0] = item;
+  }
+  __syncthreads();
+  const int32_t item = g->item[0];
+  __syncthreads();
+  if (item < 0) return false;  // every wave of the group leaves together
+  if (a.windows) {
+    // Caller triples: a star outside the batch is skipped (empty range), the range
+    // is clipped to the star's grid (in 64 bits, before narrowing).
+    const int64_t* wv = a.windows + 3 * static_cast<int64_t>(item);
+    const int64_t ws = wv[0];
+    if (ws < 0 || ws >= a.n_stars) {
+      it.star = 0;
+      it.i0 = it.i1 = 0;
+      return true;
+    }
+    const int64_t nfs = a.stars[ws].nf;
+    it.star = static_cast<int32_t>(ws);
+    it.i0 = static_cast<int32_t>(max<int64_t>(0, min<int64_t>(wv[1], nfs)));
+    it.i1 = static_cast<int32_t>(max<int64_t>(0, min<int64_t>(wv[2], nfs)));
+  } else {
+    it = a.items[item];
+  }
+  return true;
+}
+
+__device__ __forceinline__ double packed_w_unit(const StarRt& rt) {
+  unsigned long long wt_units;
+  long long st_units;
+  unpack_units(static_cast<unsigned long long>(rt.cw_total), wt_units, st_units);
+  return 1.0 / static_cast<double>(wt_units);
+}
+
+// ----------------------------------------------------------------------------
+// Wide frequencies: more fine bins than one group's LDS holds (long periods of
+// dense stars on long baselines).  One frequency is searched in passes over bin
+// ranges: pass p keeps G of the nslot = span + m_max + 1 consecutive bins starting
+// at b0 = p * span (slot i is bin (b0 + i) mod nb), so every window starting in
+// [b0, b0 + span) lies inside the slots; the fold adds only boundaries whose bin
+// falls in the range.  The best window over all passes is kept by thread 0.
+// ----------------------------------------------------------------------------
+template <bool PACKED>
+__device__ __forceinline__ void fold_wide(unsigned char* smem, double f, double nbd, int32_t nb, int32_t b0,
+                                          int32_t nslot, const double (&dtr)[kUMax], const long long (&cwr)[kUMax],
+                                          const long long (&csr)[kUMax], double dt_before, int run) {
+  int32_t prev = fold_bin_nc(dt_before, f, nbd);
+#pragma unroll
+  for (int u0 = 0; u0 < kUMax; u0 += kUGroup) {
+    if (u0 >= run) break;
+    double x[kUGroup];
+    int32_t bb[kUGroup];
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) x[v] = dtr[u0 + v] * f;
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) asm volatile("" : "+v"(x[v]));
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) x[v] = __builtin_amdgcn_fract(x[v]);
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) asm volatile("" : "+v"(x[v]));
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) x[v] = x[v] * nbd;
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) asm volatile("" : "+v"(x[v]));
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) bb[v] = static_cast<int32_t>(x[v]);
+#pragma unroll
+    for (int v = 0; v < kUGroup; ++v) {
+      const int u = u0 + v;
+      const int32_t la = (v == 0 && u0 == 0) ? prev
+                                             : __builtin_amdgcn_mov_dpp(v == 0 ? prev : bb[v - 1], 0x13C, 0xf, 0xf, false);
+      const int32_t pa = __builtin_amdgcn_update_dpp(la, bb[v], 0x138, 0xf, 0xf, false);
+      int32_t slot = bb[v] - b0;
+      if (slot < 0) slot += nb;
+      if (bb[v] != pa && slot < nslot) {
+        const uint32_t o = 8u * static_cast<uint32_t>(slot);
+        lds_add64(smem, o, cwr[u]);
+        if (!PACKED) lds_add64(smem, o + kArrBytes, csr[u]);
+      }
+    }
+    prev = bb[kUGroup - 1];
+  }
+}
+
+template <bool PACKED>
+__device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArgs& a, const StarDesc& d,
+                               const StarRt& rt, int fi, double w_unit, const double* __restrict__ dt,
+                               const int64_t* __restrict__ cw, const int64_t* __restrict__ cs, int nchunks, int run,
+                               int64_t chunk_pts, double dt_last) {
+  long long* GW = reinterpret_cast<long long*>(smem);
+  long long* GS = reinterpret_cast<long long*>(smem + kArrBytes);
+  double* HW = reinterpret_cast<double*>(smem);
+  double* HS = reinterpret_cast<double*>(smem + kArrBytes);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, T = kSearchThreads;
+  const int m_max = a.c.m_max;
+  const uint32_t m_mask = a.c.m_mask;
+  const bool dip = a.c.dip_only != 0;
+  const int64_t n = d.n;
+  double f;
+  int32_t nb;
+  grid_point(d, fi, a.c.noverlap, f, nb);
+  const double nbd = static_cast<double>(nb);
+  const int32_t blast = fold_bin_nc(dt_last, f, nbd);
+  const int mlim = min(m_max, nb - 1);
+  const int per_pass = kArrElems - m_max - 1;
+  // at least two passes, so that nslot < nb and no two slots alias one bin
+  const int passes = max(2, (nb + per_pass - 1) / per_pass);
+  const int span = (nb + passes - 1) / passes;
+  const int nslot = span + m_max + 1;  // G slots; H is defined on the first nslot - 1
+  const bool gaps = d.n_gaps > 0;
+  unsigned long long rkey = 0ull;      // running best of the passes (thread 0)
+  uint32_t rmj = ~0u;
+  double rr = 0.0, rs = 0.0;
+  for (int p = 0; p < passes; ++p) {
+    const int32_t b0 = p * span;
+    for (int i = tid; i < nslot; i += T) {
+      GW[i] = 0;
+      GS[i] = 0;
+    }
+    if (tid == 0) {
+      g->key[0] = 0ull;
+      g->mj[0] = ~0u;
+    }
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+      const int64_t wbase = static_cast<int64_t>(c) * chunk_pts + static_cast<int64_t>(wave) * 64 * run;
+      if (wbase >= n) continue;
+      const int64_t wend = min<int64_t>(n, wbase + static_cast<int64_t>(64) * run);
+      double dtr[kUMax];
+      long long cwr[kUMax], csr[kUMax];
+#pragma unroll
+      for (int u = 0; u < kUMax; ++u) {
+        const int64_t q = min<int64_t>(wbase + u * 64 + lane, wend - 1);
+        dtr[u] = dt[q];
+        cwr[u] = cw[q];
+        csr[u] = PACKED ? 0 : cs[q];
+      }
+      const double dt_before = dt[wbase > 0 ? wbase - 1 : 0];
+      fold_wide<PACKED>(smem, f, nbd, nb, b0, nslot, dtr, cwr, csr, dt_before, run);
+    }
+    __syncthreads();
+    // H on slots [0, nslot - 1), by wave 0 in place (64 slots at a time; the next
+    // chunk's first slot is read before that chunk is written).
+    if (wave == 0) {
+      for (int i0 = 0; i0 < nslot - 1; i0 += 64) {
+        const int i = i0 + lane;
+        if (i < nslot - 1) {
+          int32_t bin = b0 + i;
+          if (bin >= nb) bin -= nb;
+          unsigned long long dw = static_cast<unsigned long long>(GW[i + 1]) - static_cast<unsigned long long>(GW[i]);
+          unsigned long long ds =
+              PACKED ? 0ull : static_cast<unsigned long long>(GS[i + 1]) - static_cast<unsigned long long>(GS[i]);
+          if (bin == blast) {
+            dw += static_cast<unsigned long long>(rt.cw_total);
+            ds += static_cast<unsigned long long>(rt.cs_total);
+          }
+          if (gaps) {
+            GW[i] = static_cast<long long>(dw);
+            if (!PACKED) GS[i] = static_cast<long long>(ds);
+          } else {
+            double vw, vs;
+            if (PACKED) {
+              unpack(dw, rt.s_scale, w_unit, vw, vs);
+            } else {
+              vw = static_cast<double>(static_cast<long long>(dw)) * kW62;
+              vs = static_cast<double>(static_cast<long long>(ds)) * rt.s_scale;
+            }
+            HW[i] = vw;
+            HS[i] = vs;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (gaps) {
+      const int32_t* gl = a.gaps + d.g_off;
+      for (int idx = tid; idx < d.n_gaps; idx += T) {
+        const int32_t q = gl[idx];
+        const int32_t bq = fold_bin_nc(dt[q - 1], f, nbd);
+        const int32_t bu = fold_bin_nc(dt[q], f, nbd);
+        int32_t steps = bu - bq;
+        if (steps < 0) steps += nb;
+        if (steps > 1) {
+          const int32_t bm1 = bu == 0 ? nb - 1 : bu - 1;
+          int32_t s0 = bq - b0, s1 = bm1 - b0;
+          if (s0 < 0) s0 += nb;
+          if (s1 < 0) s1 += nb;
+          const long long ew = cw[q];
+          const long long es = PACKED ? 0 : cs[q];
+          if (s0 < nslot - 1) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&GW[s0]), static_cast<unsigned long long>(ew));
+            if (!PACKED) atomicAdd(reinterpret_cast<unsigned long long*>(&GS[s0]), static_cast<unsigned long long>(es));
+          }
+          if (s1 < nslot - 1) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&GW[s1]), 0ull - static_cast<unsigned long long>(ew));
+            if (!PACKED)
+              atomicAdd(reinterpret_cast<unsigned long long*>(&GS[s1]), 0ull - static_cast<unsigned long long>(es));
+          }
+        }
+      }
+      __syncthreads();
+      for (int i = tid; i < nslot - 1; i += T) {
+        double vw, vs;
+        if (PACKED) {
+          unpack(static_cast<unsigned long long>(GW[i]), rt.s_scale, w_unit, vw, vs);
+        } else {
+          vw = static_cast<double>(GW[i]) * kW62;
+          vs = static_cast<double>(GS[i]) * rt.s_scale;
+        }
+        HW[i] = vw;
+        HS[i] = vs;
+      }
+      __syncthreads();
+    }
+    // scan of the windows starting in [b0, b0 + span)
+    unsigned long long skey[kSlotIter];
+    uint32_t smj[kSlotIter];
+#pragma unroll
+    for (int r = 0; r < kSlotIter; ++r) {
+      const int j = tid + r * T;
+      skey[r] = 0ull;
+      smj[r] = ~0u;
+      if (j < span && b0 + j < nb) {
+        double bss = -1.0, bd = 1.0;
+        uint32_t bmj = ~0u;
+        double rv = 0.0, sv = 0.0;
+        for (int m = 1; m <= mlim; ++m) {
+          rv += HW[j + m - 1];
+          sv += HS[j + m - 1];
+          if (m_mask & (1u << (m - 1))) {
+            const double dd = fma(-rv, rv, rv);
+            const double ss = sv * sv;
+            const uint32_t mj = (static_cast<uint32_t>(m) << 20) | static_cast<uint32_t>(b0 + j);
+            if (dd > 0.0 && (!dip || sv < 0.0) && better(ss, dd, mj, bss, bd, bmj)) {
+              bss = ss;
+              bd = dd;
+              bmj = mj;
+            }
+          }
+        }
+        if (bmj != ~0u) {
+          skey[r] = static_cast<unsigned long long>(__double_as_longlong(bss / bd)) + 1ull;
+          smj[r] = bmj;
+          atomicMax(&g->key[0], skey[r]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSlotIter; ++r)
+      if (skey[r] != 0ull && skey[r] == g->key[0]) atomicMin(&g->mj[0], smj[r]);
+    __syncthreads();
+    if (tid == 0) {
+      const unsigned long long kp = g->key[0];
+      const uint32_t mp = g->mj[0];
+      if (kp != 0ull && (kp > rkey || (kp == rkey && mp < rmj))) {
+        rkey = kp;
+        rmj = mp;
+        const int m = static_cast<int>(mp >> 20);
+        const int slot = static_cast<int>(mp & 0xFFFFFu) - b0;
+        double r = 0.0, s = 0.0;
+        for (int u = 0; u < m; ++u) {
+          r += HW[slot + u];
+          s += HS[slot + u];
+        }
+        rr = r;
+        rs = s;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const int64_t out = d.f_off + fi;
+    bls_best bb;
+    bb.m = 0;
+    bb.j = -1;
+    bb.r = 0.0;
+    bb.s = 0.0;
+    double sr = 0.0;
+    if (rkey != 0ull) {
+      sr = sqrt((rs * rs) / (rr * (1.0 - rr)));
+      bb.m = static_cast<int32_t>(rmj >> 20);
+      bb.j = static_cast<int32_t>(rmj & 0xFFFFFu);
+      bb.r = rr;
+      bb.s = rs;
+    }
+    a.sr[out] = sr;
+    if (a.best) a.best[out] = bb;
+  }
+}
+
 template <bool PACKED>
 __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -456,51 +763,12 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
 
   int queue = static_cast<int>(blockIdx.x % kXcds);  // used by thread 0 only
   int probes = 0;
-  for (;;) {
-    if (tid == 0) {
-      int32_t item = -1;
-      while (probes < kXcds) {
-        const unsigned t = atomicAdd(&a.next[queue * kCounterStride], 1u);
-        const int64_t chunk = static_cast<int64_t>(t / kQueueChunk) * kXcds + queue;
-        const int64_t cand = chunk * kQueueChunk + t % kQueueChunk;
-        if (cand < a.n_items) {
-          item = static_cast<int32_t>(cand);
-          break;
-        }
-        queue = (queue + 1) % kXcds;
-        ++probes;
-      }
-      g->item[0] = item;
-    }
-    __syncthreads();
-    const int32_t item = g->item[0];
-    __syncthreads();
-    if (item < 0) break;  // every wave of the group leaves together
-
-    WorkItem it;
-    if (a.windows) {
-      // Caller triples: a star outside the batch is skipped, the range is clipped
-      // to the star's grid (in 64 bits, before narrowing).
-      const int64_t* wv = a.windows + 3 * static_cast<int64_t>(item);
-      const int64_t ws = wv[0];
-      if (ws < 0 || ws >= a.n_stars) continue;
-      const int64_t nfs = a.stars[ws].nf;
-      it.star = static_cast<int32_t>(ws);
-      it.i0 = static_cast<int32_t>(max<int64_t>(0, min<int64_t>(wv[1], nfs)));
-      it.i1 = static_cast<int32_t>(max<int64_t>(0, min<int64_t>(wv[2], nfs)));
-    } else {
-      it = a.items[item];
-    }
+  WorkItem it;
+  while (next_item(a, g, queue, probes, it)) {
     if (it.i1 <= it.i0) continue;
     const StarDesc d = a.stars[it.star];
     const StarRt rt = a.rt[it.star];
-    double w_unit = 0.0;  // packed: 1 / quantised total weight
-    if (PACKED) {
-      unsigned long long wt_units;
-      long long st_units;
-      unpack_units(static_cast<unsigned long long>(rt.cw_total), wt_units, st_units);
-      w_unit = 1.0 / static_cast<double>(wt_units);
-    }
+    const double w_unit = PACKED ? packed_w_unit(rt) : 0.0;  // packed: 1 / quantised total weight
     const int64_t n = d.n;
     const double* __restrict__ dt = a.dt + d.p_off;
     const int64_t* __restrict__ cw = a.cw + d.p_off;
@@ -510,7 +778,7 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
       double f_first;
       int32_t nb_first;
       grid_point(d, it.i0, noverlap, f_first, nb_first);
-      if (nb_first > kNbLimit || nb_first < 1) continue;  // rejected by the plan
+      if (nb_first > kNbWide || nb_first < 1) continue;  // rejected by the plan
     }
 
     // Points: wave w owns a contiguous block of 64 * run points per chunk; lane l
@@ -531,6 +799,10 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
       double f_g;
       int32_t nb_cap;
       grid_point(d, g0, noverlap, f_g, nb_cap);
+      if (nb_cap > kNbLimit) {  // searched by k_search_wide
+        F = 1;
+        continue;
+      }
       int stride = __builtin_amdgcn_readfirstlane(nb_cap + m_max);
       asm volatile("" : "+s"(stride));
       const float inv_stride = 1.0f / static_cast<float>(stride);
@@ -783,6 +1055,44 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
   }
 }
 
+// Frequencies with more fine bins than one group's LDS holds; the main kernel
+// skips them.  Same work list; nb falls with frequency, so the wide frequencies of
+// an item are a prefix of its range.
+template <bool PACKED>
+__global__ void __launch_bounds__(kSearchThreads, 4) k_search_wide(SearchArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  GroupLds* g = reinterpret_cast<GroupLds*>(smem + kGBytes);
+  const int T = kSearchThreads;
+  int queue = static_cast<int>(blockIdx.x % kXcds);  // used by thread 0 only
+  int probes = 0;
+  WorkItem it;
+  while (next_item(a, g, queue, probes, it)) {
+    if (it.i1 <= it.i0) continue;
+    const StarDesc d = a.stars[it.star];
+    double f0;
+    int32_t nb0;
+    grid_point(d, it.i0, a.c.noverlap, f0, nb0);
+    if (nb0 <= kNbLimit || nb0 > kNbWide) continue;
+    const StarRt rt = a.rt[it.star];
+    const double w_unit = PACKED ? packed_w_unit(rt) : 0.0;
+    const int64_t n = d.n;
+    const double* __restrict__ dt = a.dt + d.p_off;
+    const int64_t* __restrict__ cw = a.cw + d.p_off;
+    const int64_t* __restrict__ cs = a.cs + d.p_off;
+    const int nchunks = static_cast<int>((n + static_cast<int64_t>(T) * kUMax - 1) / (static_cast<int64_t>(T) * kUMax));
+    const int run = static_cast<int>((n + static_cast<int64_t>(T) * nchunks - 1) / (static_cast<int64_t>(T) * nchunks));
+    const int64_t chunk_pts = static_cast<int64_t>(run) * T;
+    const double dt_last = dt[n - 1];
+    for (int fi = it.i0; fi < it.i1; ++fi) {
+      double f;
+      int32_t nb;
+      grid_point(d, fi, a.c.noverlap, f, nb);
+      if (nb <= kNbLimit) break;
+      wide_frequency<PACKED>(smem, g, a, d, rt, fi, w_unit, dt, cw, cs, nchunks, run, chunk_pts, dt_last);
+    }
+  }
+}
+
 }  // namespace mi355bls
 
 using namespace mi355bls;
@@ -865,6 +1175,18 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
     hipLaunchKernelGGL(k_search<true>, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds, st, a);
   else
     hipLaunchKernelGGL(k_search<false>, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds, st, a);
+  BLS_HIP_TRY(hipGetLastError());
+  if (plan->has_wide) {
+    // frequencies with more fine bins than one LDS pass: a second persistent launch
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);
+    BLS_HIP_TRY(hipGetLastError());
+    if (plan->consts.packed)
+      hipLaunchKernelGGL(k_search_wide<true>, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds,
+                         st, a);
+    else
+      hipLaunchKernelGGL(k_search_wide<false>, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads),
+                         kSearchLds, st, a);
+  }
   BLS_HIP_TRY(hipGetLastError());
   return BLS_OK;
 }

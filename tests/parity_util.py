@@ -38,6 +38,20 @@ def window_power(t, y, w, t0, f, nb, m, j):
     return s * s / (r * (1 - r))
 
 
+def _check_argmax(label, what, i_gpu, i_orc, spec_orc):
+    """Best-frequency indices must be equal; the only exception is a near-tie of the
+    oracle's own spectrum (different point sets whose values agree to 1e-9 relative,
+    where summation order decides), which is reported."""
+    if i_gpu == i_orc:
+        return
+    assert spec_orc is not None, "%s: argmax %s %d vs %d" % (label, what, i_gpu, i_orc)
+    a, b = float(spec_orc[i_gpu]), float(spec_orc[i_orc])
+    print("%s: argmax %s differs at a near-tie: gpu %d (oracle value %.17g) vs oracle %d (%.17g)"
+          % (label, what, i_gpu, a, i_orc, b), flush=True)
+    assert abs(a - b) <= NEAR_TIE_RTOL * abs(b), "%s: argmax %s %d vs %d (%.17g vs %.17g)" % (
+        label, what, i_gpu, i_orc, a, b)
+
+
 def compare_star(ds, orc, s_gpu, s_orc, batch_star, label=""):
     """Compare one star's spectrum and summary; returns stats dict."""
     sl = ds.star_slice(s_gpu)
@@ -71,8 +85,9 @@ def compare_star(ds, orc, s_gpu, s_orc, batch_star, label=""):
     # argmax SR and S/N: exact
     R = ds._res_host[s_gpu]
     O = orc["results"][s_orc]
-    assert int(R["i_sr"]) == int(O[1]), "%s: argmax SR %d vs %d" % (label, R["i_sr"], O[1])
-    assert int(R["i_snr"]) == int(O[0]), "%s: argmax S/N %d vs %d" % (label, R["i_snr"], O[0])
+    _check_argmax(label, "SR", int(R["i_sr"]), int(O[1]), sr_o)
+    snr_o = orc["snr"][o0:o1] if "snr" in orc else None
+    _check_argmax(label, "S/N", int(R["i_snr"]), int(O[0]), snr_o)
     assert R["status"] == int(O[10])
     assert R["period"] == O[2]
     if O[10] == 0:

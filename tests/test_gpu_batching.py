@@ -114,3 +114,30 @@ def test_autotune_picks_a_candidate_and_results_do_not_change(tmp_path):
         ds = pu.run_gpu(b, _lib.default_params(tile_cells=c))
         assert np.array_equal(ds.sr_host().view(np.uint64), ref.sr_host().view(np.uint64)), c
         assert np.array_equal(ds.results_host(), ref.results_host()), c
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_wide_bin_counts_in_passes(oracle, precision):
+    # a dense star (rho = 10^1.5) over 26 sectors at 2-h cadence searched between
+    # 300 and 350 d: ~12,000 fine bins, three passes over bin ranges per frequency
+    from paper_2302_01293_amd import _lib
+    t = np.concatenate([synth.sector_times([s], 1.0 / 12) for s in range(26)])
+    rng = np.random.default_rng(21)
+    y = 1.0 + rng.normal(0, 1e-3, len(t))
+    y[((t - t[0]) % 317.0) < 0.6] -= 3e-3
+    w = np.full(len(t), 1e6)
+    b = synth.Batch(t, y, w, np.array([0, len(t)]), np.array([10 ** 1.5]), np.array([300.0]), np.array([350.0]))
+    ds = pu.fetch(pu.run_gpu(b, _lib.default_params(precision=precision)))
+    f, nb = ds.plan.frequencies(0)
+    _say("case wide nb: points", len(t), "nb", int(nb[0]), "..", int(nb[-1]), "frequencies", len(f),
+         "precision", precision)
+    assert nb[-1] > 2 * 4096
+    orc = pu.run_oracle(oracle, b)
+    if precision == 0:
+        pu.compare_star(ds, orc, 0, 0, b.star(0), "wide-nb")
+    else:
+        sr_o = orc["sr"]
+        rel = np.abs(ds._sr_host - sr_o) / np.maximum(np.abs(sr_o), 1e-300)
+        _say("wide packed max rel SR err %.3e" % rel.max())
+        assert rel.max() <= 1e-5
+        assert int(ds._res_host["i_snr"][0]) == int(orc["results"][0][0])

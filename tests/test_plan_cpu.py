@@ -121,14 +121,20 @@ def test_limits():
     assert lim["nb_max"] >= 4000 and lim["m_max"] >= 12
 
 
-def test_bin_count_beyond_limit_rejected():
-    # a two-year baseline up to 400 d at solar density needs ~4300 fine bins
+def test_wide_bin_counts_accepted():
+    # a two-year baseline up to 400 d at solar density needs ~4300 fine bins: more
+    # than one LDS pass holds, searched in passes over bin ranges
     t = np.concatenate([synth.sector_times([s], 0.5) for s in range(26)])
     y = np.ones_like(t)
-    with pytest.raises(_lib.BlsError) as e:
-        _lib.Plan(t, y, np.ones_like(t), np.array([0, len(t)]), np.array([1.0]), np.array([50.0]),
-                  np.array([400.0]))
-    assert e.value.code == -7
+    plan = _lib.Plan(t, y, np.ones_like(t), np.array([0, len(t)]), np.array([1.0]), np.array([50.0]),
+                     np.array([400.0]))
+    f, nb = plan.frequencies(0)
+    assert nb[0] > 4064 and nb[0] <= _lib.limits()["nb_max"]
+
+
+def test_limits_cover_dense_stars_on_long_baselines():
+    # rho = 10^1.5 and Pmax = 356 d need ~12,600 fine bins
+    assert _lib.limits()["nb_max"] >= 13000
 
 
 def test_tile_size_changes_only_the_work_list():
