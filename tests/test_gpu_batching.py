@@ -141,3 +141,17 @@ def test_wide_bin_counts_in_passes(oracle, precision):
         _say("wide packed max rel SR err %.3e" % rel.max())
         assert rel.max() <= 1e-5
         assert int(ds._res_host["i_snr"][0]) == int(orc["results"][0][0])
+
+
+def test_streamed_batches_match_single_runs():
+    # double-buffered stream of three batches: results equal those of each batch
+    # searched on its own
+    from paper_2302_01293_amd import stream
+    batches = [synth.ragged(4, start=200 + 10 * i) for i in range(3)]
+    res, stats = stream.run_stream(batches)
+    _say("stream stats", stats)
+    assert len(res) == 3 and stats["stars"] == 12
+    for b, r in zip(batches, res):
+        ref = pu.run_gpu(b).results_host()
+        assert np.array_equal(r["i_snr"], ref["i_snr"])
+        assert np.array_equal(r["snr"].view(np.uint64), ref["snr"].view(np.uint64))
