@@ -296,6 +296,14 @@ __device__ __forceinline__ int32_t fold_bin_nc(double dt, double f, double nbd) 
   return static_cast<int32_t>(__builtin_amdgcn_fract(dt * f) * nbd);
 }
 
+// Predecessor bins of step v (see the point layout in k_search): even steps shift
+// right by one lane, odd steps left; the lane without a source keeps `old`, the
+// same lane's bin one step earlier.
+__device__ __forceinline__ int32_t pred_bin(int v, int32_t old, int32_t src) {
+  return (v & 1) ? __builtin_amdgcn_update_dpp(old, src, 0x130, 0xf, 0xf, false)
+                 : __builtin_amdgcn_update_dpp(old, src, 0x138, 0xf, 0xf, false);
+}
+
 __device__ __forceinline__ void lds_add64(unsigned char* base, uint32_t byte_off, long long v) {
   atomicAdd(reinterpret_cast<unsigned long long*>(base + byte_off), static_cast<unsigned long long>(v));
 }
@@ -379,18 +387,16 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
 #pragma unroll
     for (int v = 0; v < kUGroup; ++v) {
       const int u = u0 + v;
-      // Predecessor bins: lane l-1 of this step (DPP wave shift right by one);
-      // lane 0 keeps the old value, lane 63 of the previous step (wave rotate).
-      const int32_t la = (v == 0 && u0 == 0) ? prev_a : __builtin_amdgcn_mov_dpp(v == 0 ? prev_a : ba[v - 1], 0x13C, 0xf, 0xf, false);
-      const int32_t pa = __builtin_amdgcn_update_dpp(la, ba[v], 0x138, 0xf, 0xf, false);
+      // Predecessor bins: even steps shift right by one lane (lane 0 keeps the
+      // previous step's value of lane 0), odd steps shift left (lane 63 keeps it).
+      const int32_t pa = pred_bin(v, v == 0 ? prev_a : ba[v - 1], ba[v]);
       if (ba[v] != pa) {
         const uint32_t o = ga + 8u * static_cast<uint32_t>(ba[v]);
         lds_add64(smem, o, cwr[u]);
         if (!PACKED) lds_add64(smem, o + kArrBytes, csr[u]);
       }
       if (TWO) {
-        const int32_t lb = (v == 0 && u0 == 0) ? prev_b : __builtin_amdgcn_mov_dpp(v == 0 ? prev_b : bb[v - 1], 0x13C, 0xf, 0xf, false);
-        const int32_t pb = __builtin_amdgcn_update_dpp(lb, bb[v], 0x138, 0xf, 0xf, false);
+        const int32_t pb = pred_bin(v, v == 0 ? prev_b : bb[v - 1], bb[v]);
         if (bb[v] != pb) {
           const uint32_t o = gb + 8u * static_cast<uint32_t>(bb[v]);
           lds_add64(smem, o, cwr[u]);
@@ -522,9 +528,7 @@ __device__ __forceinline__ void fold_wide(unsigned char* smem, double f, double 
 #pragma unroll
     for (int v = 0; v < kUGroup; ++v) {
       const int u = u0 + v;
-      const int32_t la = (v == 0 && u0 == 0) ? prev
-                                             : __builtin_amdgcn_mov_dpp(v == 0 ? prev : bb[v - 1], 0x13C, 0xf, 0xf, false);
-      const int32_t pa = __builtin_amdgcn_update_dpp(la, bb[v], 0x138, 0xf, 0xf, false);
+      const int32_t pa = pred_bin(v, v == 0 ? prev : bb[v - 1], bb[v]);
       int32_t slot = bb[v] - b0;
       if (slot < 0) slot += nb;
       if (bb[v] != pa && slot < nslot) {
@@ -585,7 +589,7 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
       long long cwr[kUMax], csr[kUMax];
 #pragma unroll
       for (int u = 0; u < kUMax; ++u) {
-        const int64_t q = min<int64_t>(wbase + u * 64 + lane, wend - 1);
+        const int64_t q = min<int64_t>(wbase + u * 64 + ((u & 1) ? 63 - lane : lane), wend - 1);
         dtr[u] = dt[q];
         cwr[u] = cw[q];
         csr[u] = PACKED ? 0 : cs[q];
@@ -781,10 +785,13 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
       if (nb_first > kNbWide || nb_first < 1) continue;  // rejected by the plan
     }
 
-    // Points: wave w owns a contiguous block of 64 * run points per chunk; lane l
-    // holds points block + 64 u + l, so a point's predecessor is in the previous
-    // lane of the same step (lane 0: lane 63 of the previous step).  Loads are
-    // coalesced and the boundaries of one step fall on consecutive bins.
+    // Points: wave w owns a contiguous block of 64 * run points per chunk; in step
+    // u lane l holds point block + 64 u + l (u even) or block + 64 u + 63 - l (u
+    // odd).  A point's predecessor is then the neighbouring lane of the same step,
+    // except for the first point of a step, whose predecessor (the last point of
+    // the previous step) sits in the same lane one step earlier: one DPP lane
+    // shift per step, with that lane keeping the previous step's value.  Loads
+    // stay coalesced and the boundaries of one step fall on consecutive bins.
     const int nchunks = static_cast<int>((n + static_cast<int64_t>(T) * kUMax - 1) / (static_cast<int64_t>(T) * kUMax));
     const int run = static_cast<int>((n + static_cast<int64_t>(T) * nchunks - 1) / (static_cast<int64_t>(T) * nchunks));
     const int64_t chunk_pts = static_cast<int64_t>(run) * T;
@@ -835,7 +842,7 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
         // Points past the block's end repeat its last point: same bin, no boundary.
 #pragma unroll
         for (int u = 0; u < kUMax; ++u) {
-          const int64_t q = min<int64_t>(wbase + u * 64 + lane, wend - 1);
+          const int64_t q = min<int64_t>(wbase + u * 64 + ((u & 1) ? 63 - lane : lane), wend - 1);
           dtr[u] = dt[q];
           cwr[u] = cw[q];
           csr[u] = PACKED ? 0 : cs[q];
@@ -977,18 +984,19 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
           const int mlim = min(m_max, nb - 1);
           const double* hwk = HW + idx;
           const double* hsk = HS + idx;
+          // Durations ascend, so a strict comparison keeps the smallest m of equal
+          // powers within the slot.
           double bss = -1.0, bd = 1.0;
-          uint32_t bmj = ~0u;
+          int bm = 0;
           double rr = 0.0, ss0 = 0.0;
           auto window = [&](int m, double rv, double sv) {
             const double dd = fma(-rv, rv, rv);  // r (1 - r) > 0  <=>  0 < r < 1
             const double ss = sv * sv;
-            const uint32_t mj = (static_cast<uint32_t>(m) << 20) | static_cast<uint32_t>(j);
             const bool ok = dd > 0.0 && (!dip || sv < 0.0);
-            if (ok && better(ss, dd, mj, bss, bd, bmj)) {
+            if (ok && ss * bd > bss * dd) {
               bss = ss;
               bd = dd;
-              bmj = mj;
+              bm = m;
             }
           };
 #pragma unroll
@@ -1004,10 +1012,10 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
             ss0 += hsk[m - 1];
             if (m_mask & (1u << (m - 1))) window(m, rr, ss0);
           }
-          if (bmj != ~0u) {
+          if (bm != 0) {
             const double p = bss / bd;
             skey[r] = static_cast<unsigned long long>(__double_as_longlong(p)) + 1ull;
-            smj[r] = bmj;
+            smj[r] = (static_cast<uint32_t>(bm) << 20) | static_cast<uint32_t>(j);
             atomicMax(&g->key[k], skey[r]);
           }
         }
