@@ -20,13 +20,13 @@ constexpr int kThreads = 1024;        // threads per prep / S/N workgroup
 constexpr int kSearchThreads = 512;   // threads per search workgroup; two workgroups per CU
                                       // (4 waves per SIMD, up to 128 registers per lane)
 constexpr int kUMax = 12;             // register-resident points per search thread
-constexpr int kGBytes = 64 * 1024;    // LDS bytes for the per-frequency accumulators
+constexpr int kGBytes = 72 * 1024;    // LDS bytes for the per-frequency accumulators (two groups per CU)
 constexpr int kNbLimit = kGBytes / 16 - 32;  // largest fine-bin count searched in one pass:
                                               // 16 B per bin, plus the replicated wrap bins
 constexpr int kNbWide = (1 << 20) - 1;       // largest fine-bin count (window start bins
                                               // are 20-bit fields); beyond kNbLimit a
                                               // frequency is searched in passes over bin ranges
-constexpr int kFMax = 32;             // most frequencies processed together
+constexpr int kFMax = 64;             // most frequencies processed together
 constexpr int kMCap = 32;             // longest duration (in fine bins)
 constexpr int64_t kMaxPoints = int64_t(1) << 30;
 constexpr int kMaxSturges = 64;

@@ -248,9 +248,9 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const StarDesc* __restrict
 //   [32K, 64K)  GS  int64 G of the residuals -> int64 H_S -> FP64 H_S
 // GS sits at a fixed offset from GW, so one address serves each atomic pair.
 // ----------------------------------------------------------------------------
-constexpr int kArrBytes = kGBytes / 2;    // 32 KB per array
+constexpr int kArrBytes = kGBytes / 2;    // 36 KB per array
 constexpr int kUGroup = 4;                // points whose bins are computed together
-constexpr int kArrElems = kArrBytes / 8;  // F * stride <= 4096
+constexpr int kArrElems = kArrBytes / 8;  // F * stride <= 4608
 constexpr int kSlotIter = kArrElems / kSearchThreads;  // slots per thread (conversion, scan)
 
 struct SearchArgs {
