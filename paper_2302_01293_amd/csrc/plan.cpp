@@ -228,6 +228,7 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
       const int64_t ng = static_cast<int64_t>(plan->gaps.size()) - d.g_off;
       if (ng > 0x7fffffff) return fail(BLS_E_UNSUPPORTED);
       d.n_gaps = static_cast<int32_t>(ng);
+      if (ng > kGapLanes) plan->has_dform = true;
     }
     d.f_off = plan->n_freq;
     plan->n_freq += d.nf;

@@ -27,6 +27,7 @@ constexpr int kNbWide = (1 << 20) - 1;       // largest fine-bin count (window s
                                               // are 20-bit fields); beyond kNbLimit a
                                               // frequency is searched in passes over bin ranges
 constexpr int kFMax = 64;             // most frequencies processed together
+constexpr int kGapLanes = 64;         // stars with more gap points fold in difference form
 constexpr int kMCap = 32;             // longest duration (in fine bins)
 constexpr int64_t kMaxPoints = int64_t(1) << 30;
 constexpr int kMaxSturges = 64;
@@ -113,6 +114,7 @@ struct bls_plan {
   std::vector<int64_t> freq_offsets;
   int64_t tile_capacity = 0;  // slots of a tiled window list: per star, its tiles + 16
   bool has_wide = false;       // some frequency has more fine bins than one LDS pass holds
+  bool has_dform = false;      // some star has more than kGapLanes gap points
   std::vector<int32_t> durations;
   mi355bls::Consts consts{};
   mi355bls::Layout layout{};

@@ -17,9 +17,12 @@
 //    enters, the telescoping sum gives the exact bin totals
 //        H[b] = G[b+1] - G[b] + [b == bin of the last point] * total.
 //    Whole cycles skipped between two points add the same value to every G and
-//    cancel; a point that skips bins inside a cycle (data gaps) adds its values
-//    to a range of G, which changes H only at the range ends (the D slots).
-//    Integer sums are exact, so the result does not depend on order.
+//    cancel; a point that skips bins inside a cycle (a data gap) changes H at two
+//    bins, the one it leaves and the one before the one it enters.  Stars where
+//    most steps skip bins (cadence coarser than the finest bins) fold in
+//    difference form: each boundary adds its values to the bin it enters and
+//    subtracts them from the bin it leaves.  Integer sums are exact, so the
+//    result does not depend on order.
 //  * Points stay in registers (dt, CW, CS) across all frequencies of a work item;
 //    only boundaries touch LDS (one 64-bit integer atomic pair per boundary).
 //  * The phase frac((t - t0) f) is computed in FP64 with the same IEEE operations
@@ -271,6 +274,9 @@ struct SearchArgs {
 };
 
 // Per-group scalars after the two accumulator arrays.
+// Gap points of a work item (up to one per lane) are kept in LDS for the whole
+// item; stars with more fold in difference form.
+constexpr int kGapCache = kGapLanes;
 struct GroupLds {
   double f[kFMax];
   int32_t nb[kFMax];
@@ -278,9 +284,17 @@ struct GroupLds {
   unsigned long long key[kFMax];      // 1 + bits of the best power (0: no valid window)
   uint32_t mj[kFMax];                 // smallest (m << 20 | j) reaching that power
   int32_t item[2];
+  double gdt0[kGapCache], gdt1[kGapCache];   // dt of the point before each gap point, and its own
+  long long gcw[kGapCache], gcs[kGapCache];  // prefix values at each gap point
 };
 constexpr size_t kSearchLds = kGBytes + sizeof(GroupLds);
 static_assert(2 * kSearchLds <= 160 * 1024, "two search workgroups per CU");
+
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int src) {
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v)), src));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v >> 32)), src));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
 
 __device__ __forceinline__ bool better(double ssa, double da, uint32_t mja, double ssb, double db, uint32_t mjb) {
   const double x = ssa * db, y = ssb * da;
@@ -308,6 +322,10 @@ __device__ __forceinline__ void lds_add64(unsigned char* base, uint32_t byte_off
   atomicAdd(reinterpret_cast<unsigned long long*>(base + byte_off), static_cast<unsigned long long>(v));
 }
 
+__device__ __forceinline__ void lds_sub64(unsigned char* base, uint32_t byte_off, long long v) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(base + byte_off), 0ull - static_cast<unsigned long long>(v));
+}
+
 // Slot index -> (frequency k, bin b) for idx < F * stride <= 4096: a float
 // estimate of idx / stride corrected by one step either way.
 __device__ __forceinline__ void slot_of(int idx, int stride, float inv_stride, int& k, int& b) {
@@ -324,11 +342,13 @@ __device__ __forceinline__ void slot_of(int idx, int stride, float inv_stride, i
 
 // One pass of the fold over the wave's block for frequencies k0 and, when TWO,
 // k0 + 1: a point whose bin differs from its predecessor's is a boundary and adds
-// its prefix values into G of its bin.
-template <bool TWO, bool PACKED>
+// its prefix values into G of its bin.  In difference form (DIFF) a boundary also
+// subtracts them from the bin it leaves, so that the array holds minus each bin's
+// sums directly (entries minus exits of every visit).  DIFF is uniform.
+template <bool TWO, bool PACKED, int UM>
 __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k0, const GroupLds* g,
-                                          const double (&dtr)[kUMax], const long long (&cwr)[kUMax],
-                                          const long long (&csr)[kUMax], double dt_before, int run) {
+                                          const double (&dtr)[UM], const long long (&cwr)[UM],
+                                          const long long (&csr)[UM], double dt_before, int run, bool DIFF) {
   const int k1 = TWO ? k0 + 1 : k0;
   const double fa = g->f[k0], fb = g->f[k1];
   const double na = static_cast<double>(g->nb[k0]), nbv = static_cast<double>(g->nb[k1]);
@@ -340,7 +360,7 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
   int32_t prev_a = fold_bin_nc(dt_before, fa, na);
   int32_t prev_b = TWO ? fold_bin_nc(dt_before, fb, nbv) : 0;
 #pragma unroll
-  for (int u0 = 0; u0 < kUMax; u0 += kUGroup) {
+  for (int u0 = 0; u0 < UM; u0 += kUGroup) {
     if (u0 >= run) break;
     // Bins of a group of steps for both frequencies, stage by stage so the
     // independent FP64 chains overlap (the empty asm statements pin the order;
@@ -394,6 +414,11 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
         const uint32_t o = ga + 8u * static_cast<uint32_t>(ba[v]);
         lds_add64(smem, o, cwr[u]);
         if (!PACKED) lds_add64(smem, o + kArrBytes, csr[u]);
+        if (DIFF) {
+          const uint32_t op = ga + 8u * static_cast<uint32_t>(pa);
+          lds_sub64(smem, op, cwr[u]);
+          if (!PACKED) lds_sub64(smem, op + kArrBytes, csr[u]);
+        }
       }
       if (TWO) {
         const int32_t pb = pred_bin(v, v == 0 ? prev_b : bb[v - 1], bb[v]);
@@ -401,6 +426,11 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
           const uint32_t o = gb + 8u * static_cast<uint32_t>(bb[v]);
           lds_add64(smem, o, cwr[u]);
           if (!PACKED) lds_add64(smem, o + kArrBytes, csr[u]);
+          if (DIFF) {
+            const uint32_t op = gb + 8u * static_cast<uint32_t>(pb);
+            lds_sub64(smem, op, cwr[u]);
+            if (!PACKED) lds_sub64(smem, op + kArrBytes, csr[u]);
+          }
         }
       }
     }
@@ -748,7 +778,10 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
   }
 }
 
-template <bool PACKED>
+// DFORM: this launch searches the stars with more than kGapLanes gap points (in
+// difference form) and skips the others; without it, the reverse.  Two kernels
+// keep the register allocation of the common case free of the second form.
+template <bool PACKED, bool DFORM>
 __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   long long* GW = reinterpret_cast<long long*>(smem);
@@ -771,6 +804,7 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
   while (next_item(a, g, queue, probes, it)) {
     if (it.i1 <= it.i0) continue;
     const StarDesc d = a.stars[it.star];
+    if ((d.n_gaps > kGapLanes) != DFORM) continue;  // the other launch's star
     const StarRt rt = a.rt[it.star];
     const double w_unit = PACKED ? packed_w_unit(rt) : 0.0;  // packed: 1 / quantised total weight
     const int64_t n = d.n;
@@ -792,10 +826,23 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
     // the previous step) sits in the same lane one step earlier: one DPP lane
     // shift per step, with that lane keeping the previous step's value.  Loads
     // stay coalesced and the boundaries of one step fall on consecutive bins.
-    const int nchunks = static_cast<int>((n + static_cast<int64_t>(T) * kUMax - 1) / (static_cast<int64_t>(T) * kUMax));
+    // The difference form keeps fewer points in registers (its fold holds more
+    // values per boundary).
+    constexpr int UM = DFORM ? 8 : kUMax;
+    const int nchunks = static_cast<int>((n + static_cast<int64_t>(T) * UM - 1) / (static_cast<int64_t>(T) * UM));
     const int run = static_cast<int>((n + static_cast<int64_t>(T) * nchunks - 1) / (static_cast<int64_t>(T) * nchunks));
     const int64_t chunk_pts = static_cast<int64_t>(run) * T;
     const double dt_last = dt[n - 1];
+    // Few gap points: keep their values in LDS for the whole item (read after the
+    // first group's set-up barrier).
+    const int ng = d.n_gaps;
+    if (!DFORM && tid < ng) {
+      const int32_t q = a.gaps[d.g_off + tid];
+      g->gdt0[tid] = dt[q - 1];
+      g->gdt1[tid] = dt[q];
+      g->gcw[tid] = cw[q];
+      g->gcs[tid] = PACKED ? 0 : cs[q];
+    }
 
     for (int g0 = it.i0, F = 0; g0 < it.i1; g0 += F) {
       // Slot geometry of this group: the fine-bin count falls with frequency, so
@@ -829,6 +876,16 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
         GS[idx] = 0;
       }
       __syncthreads();
+      // Gap points of the star: the telescoping H[b] = G[b+1] - G[b] assumes that
+      // a visit to bin b ends where a visit to bin b + 1 begins.  A point whose
+      // step from bin bp to bin b skips bins ends the visit to bp instead: its
+      // prefix values E belong to the exit of bp, not of b - 1, so H[bp] += E and
+      // H[b-1] -= E.  With at most one gap point per lane these corrections are
+      // found per frequency while G is converted to H.  Stars with more (the
+      // cadence is coarser than the finest bins, so most steps skip bins) fold in
+      // difference form instead, which needs no corrections.
+      const bool gaps_direct = !DFORM && ng > 0;
+      constexpr bool dform = DFORM;
 
       // ---- fold: a point whose bin differs from its predecessor's is a boundary
       // and adds its prefix values into G of its bin.  Two frequencies per pass
@@ -837,11 +894,11 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
         const int64_t wbase = static_cast<int64_t>(c) * chunk_pts + static_cast<int64_t>(wave) * 64 * run;
         if (wbase >= n) continue;
         const int64_t wend = min<int64_t>(n, wbase + static_cast<int64_t>(64) * run);
-        double dtr[kUMax];
-        long long cwr[kUMax], csr[kUMax];
+        double dtr[UM];
+        long long cwr[UM], csr[UM];
         // Points past the block's end repeat its last point: same bin, no boundary.
 #pragma unroll
-        for (int u = 0; u < kUMax; ++u) {
+        for (int u = 0; u < UM; ++u) {
           const int64_t q = min<int64_t>(wbase + u * 64 + ((u & 1) ? 63 - lane : lane), wend - 1);
           dtr[u] = dt[q];
           cwr[u] = cw[q];
@@ -850,121 +907,99 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
         const double dt_before = dt[wbase > 0 ? wbase - 1 : 0];
         for (int k0 = 0; k0 < F; k0 += 2) {
           if (k0 + 1 < F)
-            fold_pass<true, PACKED>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run);
+            fold_pass<true, PACKED, UM>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run, dform);
           else
-            fold_pass<false, PACKED>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run);
+            fold_pass<false, PACKED, UM>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run, dform);
         }
       }
       __syncthreads();
 
       // ---- G -> H: H[b] = G[b+1] - G[b] (+ the totals at the last point's bin;
-      // G[nb] is G[0]), one wave per frequency, in place.  A wave converts 64 bins
-      // at a time: it reads G[b] and G[b+1] of a chunk before writing the chunk, and
-      // the next chunk's first bin is still unconverted then (a wave's LDS accesses
-      // run in program order); G[0] is read before chunk 0 is written.  Without
-      // data gaps the result goes straight to FP64 with the first bins replicated
-      // after the last (windows wrap past nb - 1); otherwise int64 H first.
-      const bool gaps = d.n_gaps > 0;
-      for (int k = wave; k < F; k += kSearchThreads / 64) {
-        const int32_t nb = g->nb[k], bl = g->blast[k];
+      // G[nb] is G[0]; in difference form H[b] = -G[b] + those totals), one wave
+      // per frequency, in place.  A wave converts 64 bins at a time: it reads G[b]
+      // and G[b+1] of a chunk before writing the chunk, and the next chunk's first
+      // bin is still unconverted then (a wave's LDS accesses run in program order);
+      // G[0] is read before chunk 0 is written.  The result goes to FP64 with the
+      // first bins replicated after the last (windows wrap past nb - 1).
+      for (int k = __builtin_amdgcn_readfirstlane(wave); k < F; k += kSearchThreads / 64) {
+        const int32_t nb = __builtin_amdgcn_readfirstlane(g->nb[k]);
+        const int32_t bl = g->blast[k];
         const int mrep = min(m_max, nb - 1);
         long long* gw = GW + k * stride;
         long long* gs = GS + k * stride;
         const long long g0w = gw[0], g0s = PACKED ? 0 : gs[0];
+        // Lane l holds gap point l's two corrections at this frequency: +E at bin
+        // c0 and -E at bin c1 (-1: the point's step crosses at most one bin).
+        int32_t c0 = -1, c1 = -1;
+        unsigned long long ew = 0, es = 0;
+        if (gaps_direct && lane < ng) {
+          const double f = g->f[k];
+          const double nbd = static_cast<double>(nb);
+          const int32_t bq = fold_bin_nc(g->gdt0[lane], f, nbd);
+          const int32_t bu = fold_bin_nc(g->gdt1[lane], f, nbd);
+          int32_t steps = bu - bq;
+          if (steps < 0) steps += nb;
+          if (steps > 1) {
+            c0 = bq;
+            c1 = bu == 0 ? nb - 1 : bu - 1;
+            ew = static_cast<unsigned long long>(g->gcw[lane]);
+            es = static_cast<unsigned long long>(g->gcs[lane]);
+          }
+        }
         for (int b0 = 0; b0 < nb; b0 += 64) {
           const int b = b0 + lane;
+          // Corrections that fall in this chunk: found with one ballot per end,
+          // broadcast from the lane that holds them (rare: two per gap point).
+          unsigned long long aw = 0ull, as = 0ull;
+          if (gaps_direct) {
+            unsigned long long m0 = __ballot(static_cast<uint32_t>(c0 - b0) < 64u);
+            unsigned long long m1 = __ballot(static_cast<uint32_t>(c1 - b0) < 64u);
+            while (m0) {
+              const int src = __builtin_ctzll(m0);
+              m0 &= m0 - 1;
+              if (b == __builtin_amdgcn_readlane(c0, src)) {
+                aw += readlane_u64(ew, src);
+                as += readlane_u64(es, src);
+              }
+            }
+            while (m1) {
+              const int src = __builtin_ctzll(m1);
+              m1 &= m1 - 1;
+              if (b == __builtin_amdgcn_readlane(c1, src)) {
+                aw -= readlane_u64(ew, src);
+                as -= readlane_u64(es, src);
+              }
+            }
+          }
           if (b < nb) {
-            const long long nw = b + 1 < nb ? gw[b + 1] : g0w;
-            const long long ns = PACKED ? 0 : (b + 1 < nb ? gs[b + 1] : g0s);
-            unsigned long long dw = static_cast<unsigned long long>(nw) - static_cast<unsigned long long>(gw[b]);
+            const long long nw = dform ? 0 : (b + 1 < nb ? gw[b + 1] : g0w);
+            const long long ns = (PACKED || dform) ? 0 : (b + 1 < nb ? gs[b + 1] : g0s);
+            unsigned long long dw = static_cast<unsigned long long>(nw) - static_cast<unsigned long long>(gw[b]) + aw;
             unsigned long long ds = PACKED ? 0ull
-                                           : static_cast<unsigned long long>(ns) - static_cast<unsigned long long>(gs[b]);
+                                           : static_cast<unsigned long long>(ns) - static_cast<unsigned long long>(gs[b]) + as;
             if (b == bl) {
               dw += static_cast<unsigned long long>(rt.cw_total);
               ds += static_cast<unsigned long long>(rt.cs_total);
             }
-            if (gaps) {
-              gw[b] = static_cast<long long>(dw);
-              if (!PACKED) gs[b] = static_cast<long long>(ds);
+            double vw, vs;
+            if (PACKED) {
+              unpack(dw, rt.s_scale, w_unit, vw, vs);
             } else {
-              double vw, vs;
-              if (PACKED) {
-                unpack(dw, rt.s_scale, w_unit, vw, vs);
-              } else {
-                vw = static_cast<double>(static_cast<long long>(dw)) * kW62;
-                vs = static_cast<double>(static_cast<long long>(ds)) * rt.s_scale;
-              }
-              double* hw = reinterpret_cast<double*>(gw);
-              double* hs = reinterpret_cast<double*>(gs);
-              hw[b] = vw;
-              hs[b] = vs;
-              if (b < mrep) {
-                hw[nb + b] = vw;
-                hs[nb + b] = vs;
-              }
+              vw = static_cast<double>(static_cast<long long>(dw)) * kW62;
+              vs = static_cast<double>(static_cast<long long>(ds)) * rt.s_scale;
+            }
+            double* hw = reinterpret_cast<double*>(gw);
+            double* hs = reinterpret_cast<double*>(gs);
+            hw[b] = vw;
+            hs[b] = vs;
+            if (b < mrep) {
+              hw[nb + b] = vw;
+              hs[nb + b] = vs;
             }
           }
         }
       }
       __syncthreads();
-      if (gaps) {
-        // A point whose time step crosses more than one fine bin (a data gap)
-        // belongs to every bin in (bp, b]: G[b] got its prefix values from the
-        // fold; adding them to the skipped bins (bp, b-1] too changes H only at the
-        // two ends of that range: H[bp] += E, H[b-1] -= E.  Only points in the
-        // star's gap list can do this (their step is large compared with the bin
-        // width at the top of the grid).
-        const int32_t* gl = a.gaps + d.g_off;
-        const int total_g = F * d.n_gaps;
-        for (int idx = tid; idx < total_g; idx += T) {
-          const int k = idx / d.n_gaps;
-          const int32_t q = gl[idx - k * d.n_gaps];
-          const double f = g->f[k];
-          const int32_t nb = g->nb[k];
-          const double nbd = static_cast<double>(nb);
-          const int32_t bq = fold_bin_nc(dt[q - 1], f, nbd);
-          const int32_t bu = fold_bin_nc(dt[q], f, nbd);
-          int32_t steps = bu - bq;
-          if (steps < 0) steps += nb;
-          if (steps > 1) {
-            const int32_t bm1 = bu == 0 ? nb - 1 : bu - 1;
-            const uint32_t kb = static_cast<uint32_t>(k * stride);
-            const long long ew = cw[q];
-            atomicAdd(reinterpret_cast<unsigned long long*>(&GW[kb + bq]), static_cast<unsigned long long>(ew));
-            atomicAdd(reinterpret_cast<unsigned long long*>(&GW[kb + bm1]), 0ull - static_cast<unsigned long long>(ew));
-            if (!PACKED) {
-              const long long es = cs[q];
-              atomicAdd(reinterpret_cast<unsigned long long*>(&GS[kb + bq]), static_cast<unsigned long long>(es));
-              atomicAdd(reinterpret_cast<unsigned long long*>(&GS[kb + bm1]),
-                        0ull - static_cast<unsigned long long>(es));
-            }
-          }
-        }
-        __syncthreads();
-        // int64 H -> FP64 H in place, with the wrap replication.
-        for (int idx = tid; idx < F * stride; idx += T) {
-          int k, b;
-          slot_of(idx, stride, inv_stride, k, b);
-          const int32_t nb = g->nb[k];
-          if (b < nb) {
-            double vw, vs;
-            if (PACKED) {
-              unpack(static_cast<unsigned long long>(GW[idx]), rt.s_scale, w_unit, vw, vs);
-            } else {
-              vw = static_cast<double>(GW[idx]) * kW62;
-              vs = static_cast<double>(GS[idx]) * rt.s_scale;
-            }
-            HW[idx] = vw;
-            HS[idx] = vs;
-            if (b < min(m_max, nb - 1)) {
-              HW[idx + nb] = vw;
-              HS[idx + nb] = vs;
-            }
-          }
-        }
-        __syncthreads();
-      }
-
       // ---- scan: slot (k, j) = every duration m of the ladder starting at bin j.
       // A slot keeps its best window with the power s^2 / (r (1 - r)) compared as
       // cross products (no division); the group's best per frequency is then the
@@ -982,35 +1017,38 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
         if (k < F && j < g->nb[k]) {
           const int32_t nb = g->nb[k];
           const int mlim = min(m_max, nb - 1);
+          // H_S sits kArrElems slots after H_W: one base address for both reads.
           const double* hwk = HW + idx;
-          const double* hsk = HS + idx;
           // Durations ascend, so a strict comparison keeps the smallest m of equal
-          // powers within the slot.
+          // powers within the slot.  Branch-free: every step is read (reads past
+          // mlim stay inside the LDS allocation and are masked out).
           double bss = -1.0, bd = 1.0;
           int bm = 0;
           double rr = 0.0, ss0 = 0.0;
+          // The duration mask as a per-lane value: the compiler then selects instead
+          // of branching per duration, and the LDS reads of a slot can be issued early.
+          uint32_t mmv = m_mask;
+          asm volatile("" : "+v"(mmv));
           auto window = [&](int m, double rv, double sv) {
             const double dd = fma(-rv, rv, rv);  // r (1 - r) > 0  <=>  0 < r < 1
             const double ss = sv * sv;
-            const bool ok = dd > 0.0 && (!dip || sv < 0.0);
-            if (ok && ss * bd > bss * dd) {
-              bss = ss;
-              bd = dd;
-              bm = m;
-            }
+            // bitwise, not short-circuit: straight-line code with selects
+            const bool ok = (((mmv >> (m - 1)) & 1u) != 0u) & (m <= mlim) & (dd > 0.0) & (!dip | (sv < 0.0)) &
+                            (ss * bd > bss * dd);
+            bss = ok ? ss : bss;
+            bd = ok ? dd : bd;
+            bm = ok ? m : bm;
           };
 #pragma unroll
           for (int m = 1; m <= 12; ++m) {
-            if (m <= mlim) {
-              rr += hwk[m - 1];
-              ss0 += hsk[m - 1];
-              if (m_mask & (1u << (m - 1))) window(m, rr, ss0);
-            }
+            rr += hwk[m - 1];
+            ss0 += hwk[kArrElems + m - 1];
+            window(m, rr, ss0);
           }
           for (int m = 13; m <= mlim; ++m) {
             rr += hwk[m - 1];
-            ss0 += hsk[m - 1];
-            if (m_mask & (1u << (m - 1))) window(m, rr, ss0);
+            ss0 += hwk[kArrElems + m - 1];
+            window(m, rr, ss0);
           }
           if (bm != 0) {
             const double p = bss / bd;
@@ -1180,10 +1218,24 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);  // 8 counters
   BLS_HIP_TRY(hipGetLastError());
   if (plan->consts.packed)
-    hipLaunchKernelGGL(k_search<true>, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds, st, a);
+    hipLaunchKernelGGL((k_search<true, false>), dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds,
+                       st, a);
   else
-    hipLaunchKernelGGL(k_search<false>, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds, st, a);
+    hipLaunchKernelGGL((k_search<false, false>), dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds,
+                       st, a);
   BLS_HIP_TRY(hipGetLastError());
+  if (plan->has_dform) {
+    // stars whose steps mostly skip fine bins: a second persistent launch
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);
+    BLS_HIP_TRY(hipGetLastError());
+    if (plan->consts.packed)
+      hipLaunchKernelGGL((k_search<true, true>), dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds,
+                         st, a);
+    else
+      hipLaunchKernelGGL((k_search<false, true>), dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads),
+                         kSearchLds, st, a);
+    BLS_HIP_TRY(hipGetLastError());
+  }
   if (plan->has_wide) {
     // frequencies with more fine bins than one LDS pass: a second persistent launch
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);

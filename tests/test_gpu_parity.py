@@ -156,3 +156,50 @@ def test_cfg1_full_size_sampled(oracle):
     rec = np.abs(R["period"][strong] / b.truth["period"][strong] - 1) < 0.01
     _say("cfg1 strong injections recovered", int(rec.sum()), "/", len(strong))
     assert rec.mean() > 0.8
+
+
+def _star_with_gaps(n_holes: int, seed: int):
+    """One sector at 200 s with ``n_holes`` extra data gaps of 0.05-0.3 d (besides
+    the mid-sector one), placed away from each other and from that gap."""
+    rng = np.random.default_rng(seed)
+    t = synth.sector_times([0], synth.CADENCE_200S)
+    keep = np.ones(len(t), bool)
+    mid = int(np.argmax(np.diff(t)))
+    cand = np.arange(50, len(t) - 200, 160)
+    cand = cand[np.abs(cand - mid) > 200]
+    starts = np.sort(rng.choice(cand, size=n_holes, replace=False))
+    for s in starts:
+        keep[s:s + int(rng.integers(22, 130))] = False
+    t = t[keep]
+    y = 1.0 + rng.normal(0.0, 1e-3, len(t))
+    y[((t - t[0]) % 2.3) < 0.12] -= 2e-3
+    return t, y, np.full(len(t), 1e6)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gap_point_counts(oracle, precision):
+    # stars whose steps skip bins at 21, 64 and 65 places (up to 64 gap points
+    # the corrections are held one per lane; beyond that the int64 path runs)
+    from paper_2302_01293_amd import _lib
+    rows = [_star_with_gaps(h, 90 + h) for h in (20, 63, 64)]
+    b = synth.Batch(np.concatenate([r[0] for r in rows]), np.concatenate([r[1] for r in rows]),
+                    np.concatenate([r[2] for r in rows]),
+                    np.concatenate([[0], np.cumsum([len(r[0]) for r in rows])]).astype(np.int64),
+                    np.ones(3), np.full(3, 0.6), np.full(3, 9.0))
+    gaps = [int(np.sum(np.diff(r[0]) > 0.04)) for r in rows]
+    _say("case gap points: points", np.diff(b.offsets).tolist(), "gap points", gaps, "precision", precision)
+    assert gaps == [21, 64, 65]
+    ds = pu.fetch(pu.run_gpu(b, _lib.default_params(precision=precision)))
+    orc = pu.run_oracle(oracle, b)
+    for s in range(b.n_stars):
+        if precision == 0:
+            st = pu.compare_star(ds, orc, s, s, b.star(s), "gaps[%d]" % s)
+            _say("gaps[%d] max rel SR err %.3e" % (s, st["max_rel_sr"]))
+        else:
+            sl = ds.star_slice(s)
+            o0, o1 = int(orc["fofs"][s]), int(orc["fofs"][s + 1])
+            sr_o = orc["sr"][o0:o1]
+            rel = np.abs(ds._sr_host[sl] - sr_o) / np.maximum(np.abs(sr_o), 1e-300)
+            _say("gaps[%d] packed max rel SR err %.3e" % (s, rel.max()))
+            assert rel.max() <= pu.SR_RTOL
+            assert int(ds._res_host["i_snr"][s]) == int(orc["results"][s][0])
