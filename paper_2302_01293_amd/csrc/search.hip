@@ -340,15 +340,20 @@ __device__ __forceinline__ void slot_of(int idx, int stride, float inv_stride, i
   }
 }
 
+// Accumulation forms of the fold (uniform per launch).
+//  kTelescope: a boundary adds its prefix values to G of the bin it enters;
+//              H[b] = G[b+1] - G[b] (+ corrections at data gaps).
+//  kDiff:      a boundary subtracts its prefix values from the bin it enters and
+//              adds them to the bin it leaves, so G holds each bin's sums (exits
+//              minus entries of every visit) apart from the last visit's exit.
+constexpr int kTelescope = 0, kDiff = 1;
+
 // One pass of the fold over the wave's block for frequencies k0 and, when TWO,
-// k0 + 1: a point whose bin differs from its predecessor's is a boundary and adds
-// its prefix values into G of its bin.  In difference form (DIFF) a boundary also
-// subtracts them from the bin it leaves, so that the array holds minus each bin's
-// sums directly (entries minus exits of every visit).  DIFF is uniform.
+// k0 + 1: a point whose bin differs from its predecessor's is a boundary.
 template <bool TWO, bool PACKED, int UM>
 __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k0, const GroupLds* g,
                                           const double (&dtr)[UM], const long long (&cwr)[UM],
-                                          const long long (&csr)[UM], double dt_before, int run, bool DIFF) {
+                                          const long long (&csr)[UM], double dt_before, int run, int form) {
   const int k1 = TWO ? k0 + 1 : k0;
   const double fa = g->f[k0], fb = g->f[k1];
   const double na = static_cast<double>(g->nb[k0]), nbv = static_cast<double>(g->nb[k1]);
@@ -412,24 +417,34 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
       const int32_t pa = pred_bin(v, v == 0 ? prev_a : ba[v - 1], ba[v]);
       if (ba[v] != pa) {
         const uint32_t o = ga + 8u * static_cast<uint32_t>(ba[v]);
-        lds_add64(smem, o, cwr[u]);
-        if (!PACKED) lds_add64(smem, o + kArrBytes, csr[u]);
-        if (DIFF) {
+        if (form == kDiff) {
           const uint32_t op = ga + 8u * static_cast<uint32_t>(pa);
-          lds_sub64(smem, op, cwr[u]);
-          if (!PACKED) lds_sub64(smem, op + kArrBytes, csr[u]);
+          lds_sub64(smem, o, cwr[u]);
+          lds_add64(smem, op, cwr[u]);
+          if (!PACKED) {
+            lds_sub64(smem, o + kArrBytes, csr[u]);
+            lds_add64(smem, op + kArrBytes, csr[u]);
+          }
+        } else {
+          lds_add64(smem, o, cwr[u]);
+          if (!PACKED) lds_add64(smem, o + kArrBytes, csr[u]);
         }
       }
       if (TWO) {
         const int32_t pb = pred_bin(v, v == 0 ? prev_b : bb[v - 1], bb[v]);
         if (bb[v] != pb) {
           const uint32_t o = gb + 8u * static_cast<uint32_t>(bb[v]);
-          lds_add64(smem, o, cwr[u]);
-          if (!PACKED) lds_add64(smem, o + kArrBytes, csr[u]);
-          if (DIFF) {
+          if (form == kDiff) {
             const uint32_t op = gb + 8u * static_cast<uint32_t>(pb);
-            lds_sub64(smem, op, cwr[u]);
-            if (!PACKED) lds_sub64(smem, op + kArrBytes, csr[u]);
+            lds_sub64(smem, o, cwr[u]);
+            lds_add64(smem, op, cwr[u]);
+            if (!PACKED) {
+              lds_sub64(smem, o + kArrBytes, csr[u]);
+              lds_add64(smem, op + kArrBytes, csr[u]);
+            }
+          } else {
+            lds_add64(smem, o, cwr[u]);
+            if (!PACKED) lds_add64(smem, o + kArrBytes, csr[u]);
           }
         }
       }
@@ -781,7 +796,8 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
 // DFORM: this launch searches the stars with more than kGapLanes gap points (in
 // difference form) and skips the others; without it, the reverse.  Two kernels
 // keep the register allocation of the common case free of the second form.
-template <bool PACKED, bool DFORM>
+// DIP: only windows with s < 0 (dips) count.
+template <bool PACKED, bool DFORM, bool DIP>
 __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   long long* GW = reinterpret_cast<long long*>(smem);
@@ -795,7 +811,6 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
   const int T = kSearchThreads;
   const int m_max = a.c.m_max;
   const uint32_t m_mask = a.c.m_mask;
-  const bool dip = a.c.dip_only != 0;
   const int32_t noverlap = a.c.noverlap;
 
   int queue = static_cast<int>(blockIdx.x % kXcds);  // used by thread 0 only
@@ -885,7 +900,7 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
       // cadence is coarser than the finest bins, so most steps skip bins) fold in
       // difference form instead, which needs no corrections.
       const bool gaps_direct = !DFORM && ng > 0;
-      constexpr bool dform = DFORM;
+      constexpr int form = DFORM ? kDiff : kTelescope;
 
       // ---- fold: a point whose bin differs from its predecessor's is a boundary
       // and adds its prefix values into G of its bin.  Two frequencies per pass
@@ -907,16 +922,16 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
         const double dt_before = dt[wbase > 0 ? wbase - 1 : 0];
         for (int k0 = 0; k0 < F; k0 += 2) {
           if (k0 + 1 < F)
-            fold_pass<true, PACKED, UM>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run, dform);
+            fold_pass<true, PACKED, UM>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run, form);
           else
-            fold_pass<false, PACKED, UM>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run, dform);
+            fold_pass<false, PACKED, UM>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run, form);
         }
       }
       __syncthreads();
 
       // ---- G -> H: H[b] = G[b+1] - G[b] (+ the totals at the last point's bin;
-      // G[nb] is G[0]; in difference form H[b] = -G[b] + those totals), one wave
-      // per frequency, in place.  A wave converts 64 bins at a time: it reads G[b]
+      // G[nb] is G[0]; kDiff: H[b] = G[b] + those totals), one wave per
+      // frequency, in place.  A wave converts 64 bins at a time: it reads G[b]
       // and G[b+1] of a chunk before writing the chunk, and the next chunk's first
       // bin is still unconverted then (a wave's LDS accesses run in program order);
       // G[0] is read before chunk 0 is written.  The result goes to FP64 with the
@@ -972,11 +987,16 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
             }
           }
           if (b < nb) {
-            const long long nw = dform ? 0 : (b + 1 < nb ? gw[b + 1] : g0w);
-            const long long ns = (PACKED || dform) ? 0 : (b + 1 < nb ? gs[b + 1] : g0s);
-            unsigned long long dw = static_cast<unsigned long long>(nw) - static_cast<unsigned long long>(gw[b]) + aw;
-            unsigned long long ds = PACKED ? 0ull
-                                           : static_cast<unsigned long long>(ns) - static_cast<unsigned long long>(gs[b]) + as;
+            unsigned long long dw, ds;
+            if (DFORM) {
+              dw = static_cast<unsigned long long>(gw[b]);
+              ds = PACKED ? 0ull : static_cast<unsigned long long>(gs[b]);
+            } else {
+              const long long nw = b + 1 < nb ? gw[b + 1] : g0w;
+              const long long ns = PACKED ? 0 : (b + 1 < nb ? gs[b + 1] : g0s);
+              dw = static_cast<unsigned long long>(nw) - static_cast<unsigned long long>(gw[b]) + aw;
+              ds = PACKED ? 0ull : static_cast<unsigned long long>(ns) - static_cast<unsigned long long>(gs[b]) + as;
+            }
             if (b == bl) {
               dw += static_cast<unsigned long long>(rt.cw_total);
               ds += static_cast<unsigned long long>(rt.cs_total);
@@ -1025,16 +1045,17 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
           double bss = -1.0, bd = 1.0;
           int bm = 0;
           double rr = 0.0, ss0 = 0.0;
-          // The duration mask as a per-lane value: the compiler then selects instead
-          // of branching per duration, and the LDS reads of a slot can be issued early.
-          uint32_t mmv = m_mask;
-          asm volatile("" : "+v"(mmv));
+          // Durations of the ladder that fit this frequency (m <= mlim), as a
+          // per-lane value: the compiler then selects instead of branching per
+          // duration, and the LDS reads of a slot can be issued early.
+          uint32_t live = m_mask & (mlim >= 32 ? 0xffffffffu : ((1u << mlim) - 1u));
+          asm volatile("" : "+v"(live));
           auto window = [&](int m, double rv, double sv) {
             const double dd = fma(-rv, rv, rv);  // r (1 - r) > 0  <=>  0 < r < 1
             const double ss = sv * sv;
-            // bitwise, not short-circuit: straight-line code with selects
-            const bool ok = (((mmv >> (m - 1)) & 1u) != 0u) & (m <= mlim) & (dd > 0.0) & (!dip | (sv < 0.0)) &
-                            (ss * bd > bss * dd);
+            const bool in_ladder = (live & (1u << (m - 1))) != 0u;
+            const bool beats = ss * bd > bss * dd;
+            const bool ok = in_ladder && dd > 0.0 && beats && (!DIP || sv < 0.0);
             bss = ok ? ss : bss;
             bd = ok ? dd : bd;
             bm = ok ? m : bm;
@@ -1183,6 +1204,28 @@ extern "C" bls_status bls_prepare(bls_plan* plan, void* ws, const double* d_t, c
   return BLS_OK;
 }
 
+// The eight instantiations of k_search (packed sums, difference form, dips only).
+static void launch_search(bool packed, bool dform, bool dip, int64_t grid, hipStream_t st, const SearchArgs& a) {
+  const dim3 gd(static_cast<unsigned>(grid)), bd(kSearchThreads);
+  if (packed) {
+    if (dform) {
+      if (dip) hipLaunchKernelGGL((k_search<true, true, true>), gd, bd, kSearchLds, st, a);
+      else hipLaunchKernelGGL((k_search<true, true, false>), gd, bd, kSearchLds, st, a);
+    } else {
+      if (dip) hipLaunchKernelGGL((k_search<true, false, true>), gd, bd, kSearchLds, st, a);
+      else hipLaunchKernelGGL((k_search<true, false, false>), gd, bd, kSearchLds, st, a);
+    }
+  } else {
+    if (dform) {
+      if (dip) hipLaunchKernelGGL((k_search<false, true, true>), gd, bd, kSearchLds, st, a);
+      else hipLaunchKernelGGL((k_search<false, true, false>), gd, bd, kSearchLds, st, a);
+    } else {
+      if (dip) hipLaunchKernelGGL((k_search<false, false, true>), gd, bd, kSearchLds, st, a);
+      else hipLaunchKernelGGL((k_search<false, false, false>), gd, bd, kSearchLds, st, a);
+    }
+  }
+}
+
 extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* d_windows, int64_t n_windows,
                                        double* d_sr, bls_best* d_best, bls_stream_t stream) {
   if (!plan || !d_sr) return BLS_E_ARG;
@@ -1217,23 +1260,13 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
   const int64_t grid = std::min<int64_t>(n_items, 2 * static_cast<int64_t>(cus));
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);  // 8 counters
   BLS_HIP_TRY(hipGetLastError());
-  if (plan->consts.packed)
-    hipLaunchKernelGGL((k_search<true, false>), dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds,
-                       st, a);
-  else
-    hipLaunchKernelGGL((k_search<false, false>), dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds,
-                       st, a);
+  launch_search(plan->consts.packed != 0, false, a.c.dip_only != 0, grid, st, a);
   BLS_HIP_TRY(hipGetLastError());
   if (plan->has_dform) {
     // stars whose steps mostly skip fine bins: a second persistent launch
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);
     BLS_HIP_TRY(hipGetLastError());
-    if (plan->consts.packed)
-      hipLaunchKernelGGL((k_search<true, true>), dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds,
-                         st, a);
-    else
-      hipLaunchKernelGGL((k_search<false, true>), dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads),
-                         kSearchLds, st, a);
+    launch_search(plan->consts.packed != 0, true, a.c.dip_only != 0, grid, st, a);
     BLS_HIP_TRY(hipGetLastError());
   }
   if (plan->has_wide) {
