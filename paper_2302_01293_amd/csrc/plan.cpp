@@ -14,6 +14,7 @@
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <utility>
 
 #include "plan.hpp"
 
@@ -56,6 +57,13 @@ int32_t nbins_at(const StarDesc& d, int64_t i, int32_t noverlap) {
 double freq_at(const StarDesc& d, int64_t i) {
   const double u = d.umin + static_cast<double>(i) * d.A;
   return (u * u) * u;
+}
+
+// Smallest time step that can advance the phase by 0.99 fine bins at frequencies
+// up to f (f nb <= noverlap f^(1/3) / kq + f, increasing in f).
+double gap_threshold(const StarDesc& d, double f, int32_t noverlap) {
+  const double fnb = static_cast<double>(noverlap) * std::cbrt(f) / d.kq + f;
+  return 0.99 / fnb;
 }
 
 bool valid_params(const bls_params& p) {
@@ -135,6 +143,7 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
   }
 
   const double ksun = k_sun();
+  std::vector<double> gap_steps;  // time step of each gap point, parallel to plan->gaps
   int64_t off = 0;
   for (int32_t s = 0; s < n_stars; ++s) {
     const bls_star& st = stars[s];
@@ -212,23 +221,33 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
     d.sturges = std::max(1, std::min(sturges, kMaxSturges));
     // Gap list: points whose time step may advance the phase by a whole fine bin or
     // more at some grid frequency.  The phase advance of a step dt is dt f nb, and
-    // f nb <= noverlap f^(1/3) / kq + f, largest at the top of the grid; steps below
-    // 0.99 / that bound move at most one bin everywhere.
+    // f nb <= noverlap f^(1/3) / kq + f, which grows with f; steps below 0.99 / that
+    // bound at the top of the grid move at most one bin everywhere.  The list is
+    // ordered by step, largest first, so that the points that can skip bins below
+    // any lower frequency form a prefix of it.
     {
       const double fmax = freq_at(d, d.nf - 1);
-      const double fnb = static_cast<double>(p->noverlap) * std::cbrt(fmax) / d.kq + fmax;
-      const double thr = 0.99 / fnb;
+      const double thr = gap_threshold(d, fmax, p->noverlap);
       d.g_off = static_cast<int64_t>(plan->gaps.size());
       try {
+        std::vector<std::pair<double, int32_t>> list;
         for (int64_t i = 1; i < n; ++i)
-          if (ts[i] - ts[i - 1] >= thr) plan->gaps.push_back(static_cast<int32_t>(i));
+          if (ts[i] - ts[i - 1] >= thr) list.emplace_back(ts[i] - ts[i - 1], static_cast<int32_t>(i));
+        std::stable_sort(list.begin(), list.end(),
+                         [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
+                           return a.first > b.first;
+                         });
+        for (const auto& e : list) {
+          plan->gaps.push_back(e.second);
+          gap_steps.push_back(e.first);
+        }
       } catch (...) {
         return fail(BLS_E_NOMEM);
       }
       const int64_t ng = static_cast<int64_t>(plan->gaps.size()) - d.g_off;
       if (ng > 0x7fffffff) return fail(BLS_E_UNSUPPORTED);
       d.n_gaps = static_cast<int32_t>(ng);
-      if (ng > kGapLanes) plan->has_dform = true;
+      if (ng > kGapLanes) plan->has_dform_star = true;
     }
     d.f_off = plan->n_freq;
     plan->n_freq += d.nf;
@@ -251,7 +270,14 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
       plan->tile_capacity += (d.nf + per - 1) / per + kWindowSlack;
       for (int64_t i0 = 0; i0 < d.nf; i0 += per) {
         const int64_t i1 = std::min<int64_t>(d.nf, i0 + per);
-        plan->items.push_back(WorkItem{s, static_cast<int32_t>(i0), static_cast<int32_t>(i1), 0});
+        // gap points that can skip bins somewhere in [i0, i1): those whose step
+        // reaches the threshold at the item's top frequency
+        const double thr = gap_threshold(d, freq_at(d, i1 - 1), p->noverlap);
+        const double* st0 = gap_steps.data() + d.g_off;
+        const int32_t ng = static_cast<int32_t>(
+            std::partition_point(st0, st0 + d.n_gaps, [thr](double v) { return v >= thr; }) - st0);
+        if (ng > kGapLanes) plan->has_dform = true;
+        plan->items.push_back(WorkItem{s, static_cast<int32_t>(i0), static_cast<int32_t>(i1), ng});
       }
     }
   } catch (...) {

@@ -73,7 +73,8 @@ constexpr int kPackWBits = 27;
 
 // A work item: frequencies [i0, i1) of one star.
 struct WorkItem {
-  int32_t star, i0, i1, pad;
+  int32_t star, i0, i1;
+  int32_t n_gaps;  // leading entries of the star's gap list that matter in [i0, i1)
 };
 
 // Scalars shared by every kernel of a plan.
@@ -110,11 +111,13 @@ struct bls_plan {
   int64_t n_freq = 0;
   std::vector<mi355bls::StarDesc> stars;
   std::vector<mi355bls::WorkItem> items;
-  std::vector<int32_t> gaps;  // per star (CSR by StarDesc::g_off): point indices n >= 1
+  std::vector<int32_t> gaps;  // per star (CSR by StarDesc::g_off): point indices n >= 1,
+                              // largest time step first
   std::vector<int64_t> freq_offsets;
   int64_t tile_capacity = 0;  // slots of a tiled window list: per star, its tiles + 16
   bool has_wide = false;       // some frequency has more fine bins than one LDS pass holds
-  bool has_dform = false;      // some star has more than kGapLanes gap points
+  bool has_dform = false;      // some work item has more than kGapLanes gap points
+  bool has_dform_star = false; // some star has (caller windows use the star's count)
   std::vector<int32_t> durations;
   mi355bls::Consts consts{};
   mi355bls::Layout layout{};

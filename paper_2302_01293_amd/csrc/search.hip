@@ -519,12 +519,14 @@ __device__ bool next_item(const SearchArgs& a, GroupLds* g, int& queue, int& pro
     if (ws < 0 || ws >= a.n_stars) {
       it.star = 0;
       it.i0 = it.i1 = 0;
+      it.n_gaps = -1;
       return true;
     }
     const int64_t nfs = a.stars[ws].nf;
     it.star = static_cast<int32_t>(ws);
     it.i0 = static_cast<int32_t>(max<int64_t>(0, min<int64_t>(wv[1], nfs)));
     it.i1 = static_cast<int32_t>(max<int64_t>(0, min<int64_t>(wv[2], nfs)));
+    it.n_gaps = -1;
   } else {
     it = a.items[item];
   }
@@ -819,7 +821,10 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
   while (next_item(a, g, queue, probes, it)) {
     if (it.i1 <= it.i0) continue;
     const StarDesc d = a.stars[it.star];
-    if ((d.n_gaps > kGapLanes) != DFORM) continue;  // the other launch's star
+    // Gap points that matter for this item: a prefix of the star's list (caller
+    // windows, whose count the plan does not know, take the whole list).
+    const int ng = it.n_gaps >= 0 ? it.n_gaps : d.n_gaps;
+    if ((ng > kGapLanes) != DFORM) continue;  // the other launch's item
     const StarRt rt = a.rt[it.star];
     const double w_unit = PACKED ? packed_w_unit(rt) : 0.0;  // packed: 1 / quantised total weight
     const int64_t n = d.n;
@@ -850,7 +855,6 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
     const double dt_last = dt[n - 1];
     // Few gap points: keep their values in LDS for the whole item (read after the
     // first group's set-up barrier).
-    const int ng = d.n_gaps;
     if (!DFORM && tid < ng) {
       const int32_t q = a.gaps[d.g_off + tid];
       g->gdt0[tid] = dt[q - 1];
@@ -1262,7 +1266,7 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
   BLS_HIP_TRY(hipGetLastError());
   launch_search(plan->consts.packed != 0, false, a.c.dip_only != 0, grid, st, a);
   BLS_HIP_TRY(hipGetLastError());
-  if (plan->has_dform) {
+  if (d_windows ? plan->has_dform_star : plan->has_dform) {
     // stars whose steps mostly skip fine bins: a second persistent launch
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);
     BLS_HIP_TRY(hipGetLastError());
