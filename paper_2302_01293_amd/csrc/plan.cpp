@@ -143,7 +143,7 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
   }
 
   const double ksun = k_sun();
-  std::vector<double> gap_steps;  // time step of each gap point, parallel to plan->gaps
+  std::vector<double>& gap_steps = plan->gap_steps;
   int64_t off = 0;
   for (int32_t s = 0; s < n_stars; ++s) {
     const bls_star& st = stars[s];
@@ -300,6 +300,8 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
   pos = align256(pos + int64_t(sizeof(WorkItem)) * int64_t(plan->items.size()));
   L.gaps = pos;
   pos = align256(pos + 4 * std::max<int64_t>(1, static_cast<int64_t>(plan->gaps.size())));
+  L.gap_steps = pos;
+  pos = align256(pos + 8 * std::max<int64_t>(1, static_cast<int64_t>(plan->gaps.size())));
   L.dt = pos;
   pos = align256(pos + 8 * plan->n_points);
   L.cw = pos;

@@ -88,7 +88,7 @@ struct Consts {
 };
 
 struct Layout {  // byte offsets inside the device workspace
-  int64_t stars, rt, items, gaps, dt, cw, cs, rho, counter, total;
+  int64_t stars, rt, items, gaps, gap_steps, dt, cw, cs, rho, counter, total;
 };
 
 // Records the HIP error code of a failed HIP call (per thread) and returns
@@ -113,6 +113,7 @@ struct bls_plan {
   std::vector<mi355bls::WorkItem> items;
   std::vector<int32_t> gaps;  // per star (CSR by StarDesc::g_off): point indices n >= 1,
                               // largest time step first
+  std::vector<double> gap_steps;  // the time step of each entry of gaps
   std::vector<int64_t> freq_offsets;
   int64_t tile_capacity = 0;  // slots of a tiled window list: per star, its tiles + 16
   bool has_wide = false;       // some frequency has more fine bins than one LDS pass holds

@@ -264,6 +264,7 @@ struct SearchArgs {
   const int64_t* cw;
   const int64_t* cs;
   const int32_t* gaps;     // per-star lists of points whose step can skip bins
+  const double* gap_steps; // their time steps (each list ordered largest first)
   const int64_t* windows;  // optional (star, i0, i1) triples replacing items
   double* sr;
   bls_best* best;
@@ -488,9 +489,31 @@ __device__ __forceinline__ void unpack(unsigned long long h, double s_scale, dou
   vs = static_cast<double>(ssum) * s_scale;
 }
 
+// Number of leading entries >= thr of steps[0, ng) (ordered largest first), by the
+// 64 lanes of one wave: each round probes 64 evenly spaced entries and keeps the
+// interval where the entries fall below thr (three rounds cover 262,144 entries).
+__device__ int count_at_least(const double* __restrict__ steps, int ng, double thr) {
+  const int lane = threadIdx.x & 63;
+  int lo = 0, hi = ng;  // the count lies in [lo, hi]
+  while (lo < hi) {
+    const int step = (hi - lo + 63) / 64;
+    const int pos = lo + lane * step;
+    const unsigned long long m = __ballot(pos < hi && steps[pos] >= thr);
+    const int c = __popcll(m);  // probes below the count (a prefix of the lanes)
+    if (c == 0) break;          // steps[lo] < thr: the count is lo
+    const int nlo = lo + (c - 1) * step + 1;
+    hi = min(hi, lo + c * step);
+    lo = nlo;
+  }
+  return lo;
+}
+
 // Next work item of this workgroup (the same for all its threads), or false when
-// every queue is empty.  `queue` and `probes` are thread 0's state.
-__device__ bool next_item(const SearchArgs& a, GroupLds* g, int& queue, int& probes, WorkItem& it) {
+// every queue is empty.  `queue` and `probes` are thread 0's state.  With
+// `count_gaps`, a caller window also gets the number of gap points that can skip
+// bins in its frequency range (plan items carry theirs).
+__device__ bool next_item(const SearchArgs& a, GroupLds* g, int& queue, int& probes, WorkItem& it,
+                          bool count_gaps = false) {
   const int tid = threadIdx.x;
   if (tid == 0) {
     int32_t item = -1;
@@ -522,11 +545,26 @@ __device__ bool next_item(const SearchArgs& a, GroupLds* g, int& queue, int& pro
       it.n_gaps = -1;
       return true;
     }
-    const int64_t nfs = a.stars[ws].nf;
+    const StarDesc& d = a.stars[ws];
+    const int64_t nfs = d.nf;
     it.star = static_cast<int32_t>(ws);
     it.i0 = static_cast<int32_t>(max<int64_t>(0, min<int64_t>(wv[1], nfs)));
     it.i1 = static_cast<int32_t>(max<int64_t>(0, min<int64_t>(wv[2], nfs)));
     it.n_gaps = -1;
+    if (count_gaps && it.i1 > it.i0 && d.n_gaps > 0) {
+      // the same bound as the plan's: steps below 0.99 / (f nb) at the range's top
+      // frequency, f nb <= noverlap f^(1/3) / kq + f, move at most one bin
+      if (tid < 64) {
+        double f;
+        int32_t nb;
+        grid_point(d, it.i1 - 1, a.c.noverlap, f, nb);
+        const double thr = 0.99 / (static_cast<double>(a.c.noverlap) * cbrt(f) / d.kq + f);
+        const int c = count_at_least(a.gap_steps + d.g_off, d.n_gaps, thr);
+        if (tid == 0) g->item[1] = c;
+      }
+      __syncthreads();
+      it.n_gaps = g->item[1];
+    }
   } else {
     it = a.items[item];
   }
@@ -818,11 +856,10 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
   int queue = static_cast<int>(blockIdx.x % kXcds);  // used by thread 0 only
   int probes = 0;
   WorkItem it;
-  while (next_item(a, g, queue, probes, it)) {
+  while (next_item(a, g, queue, probes, it, true)) {
     if (it.i1 <= it.i0) continue;
     const StarDesc d = a.stars[it.star];
-    // Gap points that matter for this item: a prefix of the star's list (caller
-    // windows, whose count the plan does not know, take the whole list).
+    // Gap points that matter for this item: a prefix of the star's list.
     const int ng = it.n_gaps >= 0 ? it.n_gaps : d.n_gaps;
     if ((ng > kGapLanes) != DFORM) continue;  // the other launch's item
     const StarRt rt = a.rt[it.star];
@@ -1186,9 +1223,12 @@ extern "C" bls_status bls_plan_upload(bls_plan* plan, void* ws, int64_t bytes, b
   if (!plan->items.empty())
     BLS_HIP_TRY(hipMemcpyAsync(base + plan->layout.items, plan->items.data(),
                                sizeof(WorkItem) * plan->items.size(), hipMemcpyHostToDevice, st));
-  if (!plan->gaps.empty())
+  if (!plan->gaps.empty()) {
     BLS_HIP_TRY(hipMemcpyAsync(base + plan->layout.gaps, plan->gaps.data(),
                                sizeof(int32_t) * plan->gaps.size(), hipMemcpyHostToDevice, st));
+    BLS_HIP_TRY(hipMemcpyAsync(base + plan->layout.gap_steps, plan->gap_steps.data(),
+                               sizeof(double) * plan->gap_steps.size(), hipMemcpyHostToDevice, st));
+  }
   plan->uploaded_to = ws;
   return BLS_OK;
 }
@@ -1247,6 +1287,7 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
   a.cw = reinterpret_cast<const int64_t*>(base + L.cw);
   a.cs = reinterpret_cast<const int64_t*>(base + L.cs);
   a.gaps = reinterpret_cast<const int32_t*>(base + L.gaps);
+  a.gap_steps = reinterpret_cast<const double*>(base + L.gap_steps);
   a.windows = d_windows;
   a.sr = d_sr;
   a.best = d_best;
