@@ -33,13 +33,18 @@ COUNTERS = os.path.join(ROOT, "profiles", "k_search_cfg1_counters.json")
 
 
 def search_sources_digest() -> str:
-    """Digest of the sources that define the search kernel (counters go stale when
-    they change)."""
+    """Digest of the code (comments and blank lines removed) of the sources that
+    define the search kernel: the counters go stale when it changes."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for rel in ("paper_2302_01293_amd/csrc/search.hip", "paper_2302_01293_amd/csrc/plan.hpp"):
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].strip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 

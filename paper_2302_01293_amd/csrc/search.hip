@@ -244,11 +244,12 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const StarDesc* __restrict
 // ----------------------------------------------------------------------------
 // Fused fold -> boundary accumulation -> H -> duration/phase scan.
 // A persistent grid pulls work items (a frequency range of one star) from a
-// counter; 64 KB of LDS per workgroup lets two workgroups share a CU, so one can
-// fold (LDS-atomic bound) while the other scans (VALU bound).  LDS layout for the
-// F frequencies of the current group, `stride` slots each (k-major):
-//   [  0, 32K)  GW  int64 G of the weights   -> int64 H_W -> FP64 H_W
-//   [32K, 64K)  GS  int64 G of the residuals -> int64 H_S -> FP64 H_S
+// counter; 72 KB of accumulators (plus the group's scalars) per workgroup lets two
+// workgroups share a CU, so one can fold (LDS-atomic bound) while the other scans
+// (VALU bound).  LDS layout for the F frequencies of the current group, `stride`
+// slots each (k-major):
+//   [  0, 36K)  GW  int64 G of the weights   -> FP64 H_W
+//   [36K, 72K)  GS  int64 G of the residuals -> FP64 H_S
 // GS sits at a fixed offset from GW, so one address serves each atomic pair.
 // ----------------------------------------------------------------------------
 constexpr int kArrBytes = kGBytes / 2;    // 36 KB per array
