@@ -86,6 +86,19 @@ class Batch:
                      self.pmax[stars].copy(), truth)
 
 
+def concat(batches) -> Batch:
+    """One batch holding the stars of several (truth keys common to all are kept)."""
+    keys = set.intersection(*[set(b.truth) for b in batches])
+    offs = [0]
+    for b in batches:
+        offs.extend(offs[-1] + np.asarray(b.offsets[1:]))
+    return Batch(np.concatenate([b.t for b in batches]), np.concatenate([b.y for b in batches]),
+                 np.concatenate([b.w for b in batches]), np.asarray(offs, np.int64),
+                 np.concatenate([b.rho for b in batches]), np.concatenate([b.pmin for b in batches]),
+                 np.concatenate([b.pmax for b in batches]),
+                 {k: np.concatenate([np.asarray(b.truth[k]) for b in batches]) for k in sorted(keys)})
+
+
 def _star_rngs(workload: str, n: int, start: int = 0):
     ss = np.random.SeedSequence(ROOT_SEED).spawn(len(WORKLOADS))[WORKLOADS[workload]]
     kids = ss.spawn(start + n)[start:]

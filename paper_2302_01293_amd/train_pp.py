@@ -4,8 +4,10 @@ the plain search on held-out light curves.
     python -m paper_2302_01293_amd.train_pp --n-train 8192 --n-eval 2048 \
         --max-sectors 3 --epochs 40 --out pp_weights.npy --report pp_report.json
 
-Training light curves are the trapezoid-injection recipe of ``synth.config3``;
-labels come from the plain search on each of them (``learned.plain_labels``).
+Training light curves are the trapezoid-injection recipe of ``synth.config3``, or
+with ``--recipe mixed`` half of them and half one-sector box-injection stars of
+the ``synth.config1`` recipe (seeds disjoint from the benchmark's); labels come
+from the plain search on each of them (``learned.plain_labels``).
 The report gives, for the untrained and the trained network on the evaluation
 stars: recovery of the plain detections, the fraction of stars that fell back
 to the full grid, the searched fraction of the grid, and the device time of both
@@ -19,6 +21,12 @@ import sys
 import time
 
 import numpy as np
+
+
+# one-sector training and evaluation stars come from seeds far from the
+# benchmark's (stars 0 .. 4095 of the same recipe)
+CFG1_TRAIN_START = 100_000
+CFG1_EVAL_START = 150_000
 
 
 def log(*a):
@@ -64,6 +72,7 @@ def main(argv=None):
     ap.add_argument("--sweep", default="", help="comma-separated confidence thresholds to evaluate after training")
     ap.add_argument("--topk", type=int, default=8)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--recipe", choices=("cfg3", "mixed"), default="cfg3")
     ap.add_argument("--out", default="")
     ap.add_argument("--report", default="")
     args = ap.parse_args(argv)
@@ -72,8 +81,15 @@ def main(argv=None):
     from . import learned, synth
     assert torch.cuda.is_available(), "training runs on the GPU"
     t0 = time.time()
-    train = synth.config3(args.n_train, start=0, max_sectors=args.max_sectors)
     evalb = synth.config3(args.n_eval, start=args.n_train, max_sectors=args.max_sectors)
+    eval1 = None
+    if args.recipe == "mixed":
+        half = args.n_train // 2
+        train = synth.concat([synth.config3(half, start=0, max_sectors=args.max_sectors),
+                              synth.config1(args.n_train - half, start=CFG1_TRAIN_START)])
+        eval1 = synth.config1(args.n_eval, start=CFG1_EVAL_START)
+    else:
+        train = synth.config3(args.n_train, start=0, max_sectors=args.max_sectors)
     log("generated %d + %d light curves (%.1f s)" % (train.n_stars, evalb.n_stars, time.time() - t0))
     t1 = time.time()
     x, lag, labels, _ = labelled(train)
@@ -90,10 +106,14 @@ def main(argv=None):
     sweep = {}
     for c in [float(v) for v in args.sweep.split(",") if v]:
         sweep[str(c)] = evaluate(evalb, net, "trained, conf %.3f" % c, c, args.topk)
+    sweep1 = {}
+    if eval1 is not None:
+        for c in [args.conf] + [float(v) for v in args.sweep.split(",") if v]:
+            sweep1[str(c)] = evaluate(eval1, net, "trained, one-sector boxes, conf %.3f" % c, c, args.topk)
     rep = dict(n_train=train.n_stars, n_eval=evalb.n_stars, max_sectors=args.max_sectors, epochs=args.epochs,
                batch=args.batch, lr=args.lr, conf=args.conf, steps=net.step, loss_first=hist[0],
                loss_last=hist[-1], label_periods=int((labels >= 0).sum()), untrained=before, trained=after, sweep=sweep,
-               topk=args.topk)
+               topk=args.topk, recipe=args.recipe, sweep_one_sector=sweep1)
     if args.out:
         np.save(args.out, net.params_host())
     if args.report:

@@ -159,3 +159,17 @@ def test_autotune_cache_and_sampling(tmp_path):
     assert autotune.load_cache(path) == {}
     autotune.save_cache(path, {k1: {"tile_cells": 123}})
     assert autotune.load_cache(path)[k1]["tile_cells"] == 123
+
+
+def test_concat_keeps_stars_and_common_truth():
+    from paper_2302_01293_amd import synth
+    a = synth.config3(5, start=0, max_sectors=2)
+    b = synth.config1(3, start=100_000)
+    c = synth.concat([a, b])
+    assert c.n_stars == 8 and c.n_points == a.n_points + b.n_points
+    for s in range(5):
+        assert all(np.array_equal(u, v) for u, v in zip(c.star(s), a.star(s)))
+    for s in range(3):
+        assert all(np.array_equal(u, v) for u, v in zip(c.star(5 + s), b.star(s)))
+    assert set(c.truth) == set(a.truth) & set(b.truth)
+    assert np.array_equal(c.truth["period"][5:], b.truth["period"], equal_nan=True)
