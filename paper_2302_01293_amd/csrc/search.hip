@@ -370,8 +370,8 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
   for (int u0 = 0; u0 < UM; u0 += kUGroup) {
     if (u0 >= run) break;
     // Bins of a group of steps for both frequencies, stage by stage so the
-    // independent FP64 chains overlap (the empty asm statements pin the order;
-    // without them the compiler sinks each chain into its branch).
+    // independent FP64 chains overlap (the compiler's own schedule of these
+    // stages measured faster than one pinned with empty asm statements).
     double xa[kUGroup], xb[kUGroup];
     int32_t ba[kUGroup], bb[kUGroup];
 #pragma unroll
@@ -381,18 +381,8 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
     }
 #pragma unroll
     for (int v = 0; v < kUGroup; ++v) {
-      asm volatile("" : "+v"(xa[v]));
-      if (TWO) asm volatile("" : "+v"(xb[v]));
-    }
-#pragma unroll
-    for (int v = 0; v < kUGroup; ++v) {
       xa[v] = __builtin_amdgcn_fract(xa[v]);
       if (TWO) xb[v] = __builtin_amdgcn_fract(xb[v]);
-    }
-#pragma unroll
-    for (int v = 0; v < kUGroup; ++v) {
-      asm volatile("" : "+v"(xa[v]));
-      if (TWO) asm volatile("" : "+v"(xb[v]));
     }
 #pragma unroll
     for (int v = 0; v < kUGroup; ++v) {
@@ -401,16 +391,9 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
     }
 #pragma unroll
     for (int v = 0; v < kUGroup; ++v) {
-      asm volatile("" : "+v"(xa[v]));
-      if (TWO) asm volatile("" : "+v"(xb[v]));
-    }
-#pragma unroll
-    for (int v = 0; v < kUGroup; ++v) {
       ba[v] = static_cast<int32_t>(xa[v]);
       bb[v] = TWO ? static_cast<int32_t>(xb[v]) : 0;
     }
-#pragma unroll
-    for (int v = 0; v < kUGroup; ++v) asm volatile("" ::"v"(ba[v]), "v"(bb[v]));
 #pragma unroll
     for (int v = 0; v < kUGroup; ++v) {
       const int u = u0 + v;
