@@ -254,6 +254,7 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const StarDesc* __restrict
 // ----------------------------------------------------------------------------
 constexpr int kArrBytes = kGBytes / 2;    // 36 KB per array
 constexpr int kUGroup = 4;                // points whose bins are computed together
+static_assert(kUMax % kUGroup == 0, "the folds take whole groups of steps");
 constexpr int kArrElems = kArrBytes / 8;  // F * stride <= 4608
 constexpr int kSlotIter = kArrElems / kSearchThreads;  // slots per thread (conversion, scan)
 
@@ -870,6 +871,7 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
     // The difference form keeps fewer points in registers (its fold holds more
     // values per boundary).
     constexpr int UM = DFORM ? 8 : kUMax;
+    static_assert(UM % kUGroup == 0, "the fold takes whole groups of steps");
     const int nchunks = static_cast<int>((n + static_cast<int64_t>(T) * UM - 1) / (static_cast<int64_t>(T) * UM));
     const int run = static_cast<int>((n + static_cast<int64_t>(T) * nchunks - 1) / (static_cast<int64_t>(T) * nchunks));
     const int64_t chunk_pts = static_cast<int64_t>(run) * T;
