@@ -17,10 +17,11 @@ namespace mi355bls {
 
 // Compiled limits.
 constexpr int kThreads = 1024;        // threads per prep / S/N workgroup
-constexpr int kSearchThreads = 512;   // threads per search workgroup; two workgroups per CU
-                                      // (4 waves per SIMD, up to 128 registers per lane)
-constexpr int kUMax = 12;             // register-resident points per search thread
-constexpr int kGBytes = 72 * 1024;    // LDS bytes for the per-frequency accumulators (two groups per CU)
+constexpr int kSearchThreads = 512;   // threads per search workgroup; three workgroups per CU
+                                      // (6 waves per SIMD, up to 80 registers per lane)
+constexpr int kSearchGroupsPerCu = 3;
+constexpr int kUMax = 8;              // register-resident points per search thread
+constexpr int kGBytes = 48 * 1024;    // LDS bytes for the per-frequency accumulators (three groups per CU)
 constexpr int kNbLimit = kGBytes / 16 - 32;  // largest fine-bin count searched in one pass:
                                               // 16 B per bin, plus the replicated wrap bins
 constexpr int kNbWide = (1 << 20) - 1;       // largest fine-bin count (window start bins

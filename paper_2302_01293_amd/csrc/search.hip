@@ -244,18 +244,18 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const StarDesc* __restrict
 // ----------------------------------------------------------------------------
 // Fused fold -> boundary accumulation -> H -> duration/phase scan.
 // A persistent grid pulls work items (a frequency range of one star) from a
-// counter; 72 KB of accumulators (plus the group's scalars) per workgroup lets two
-// workgroups share a CU, so one can fold (LDS-atomic bound) while the other scans
-// (VALU bound).  LDS layout for the F frequencies of the current group, `stride`
-// slots each (k-major):
-//   [  0, 36K)  GW  int64 G of the weights   -> FP64 H_W
-//   [36K, 72K)  GS  int64 G of the residuals -> FP64 H_S
+// counter; 48 KB of accumulators (plus the group's scalars) per workgroup and at
+// most 80 registers per lane let three workgroups share a CU (six waves per SIMD),
+// so some fold (LDS-atomic bound) while others scan (VALU bound).  LDS layout for
+// the F frequencies of the current group, `stride` slots each (k-major):
+//   [  0, 24K)  GW  int64 G of the weights   -> FP64 H_W
+//   [24K, 48K)  GS  int64 G of the residuals -> FP64 H_S
 // GS sits at a fixed offset from GW, so one address serves each atomic pair.
 // ----------------------------------------------------------------------------
 constexpr int kArrBytes = kGBytes / 2;    // 36 KB per array
 constexpr int kUGroup = 4;                // points whose bins are computed together
 static_assert(kUMax % kUGroup == 0, "the folds take whole groups of steps");
-constexpr int kArrElems = kArrBytes / 8;  // F * stride <= 4608
+constexpr int kArrElems = kArrBytes / 8;  // F * stride <= 3072
 constexpr int kSlotIter = kArrElems / kSearchThreads;  // slots per thread (conversion, scan)
 
 struct SearchArgs {
@@ -291,7 +291,7 @@ struct GroupLds {
   long long gcw[kGapCache], gcs[kGapCache];  // prefix values at each gap point
 };
 constexpr size_t kSearchLds = kGBytes + sizeof(GroupLds);
-static_assert(2 * kSearchLds <= 160 * 1024, "two search workgroups per CU");
+static_assert(kSearchGroupsPerCu * kSearchLds <= 160 * 1024, "search workgroups per CU");
 
 __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int src) {
   const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v)), src));
@@ -823,7 +823,7 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
 // keep the register allocation of the common case free of the second form.
 // DIP: only windows with s < 0 (dips) count.
 template <bool PACKED, bool DFORM, bool DIP>
-__global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
+__global__ void __launch_bounds__(kSearchThreads, 2 * kSearchGroupsPerCu) k_search(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   long long* GW = reinterpret_cast<long long*>(smem);
   long long* GS = reinterpret_cast<long long*>(smem + kArrBytes);
@@ -870,7 +870,7 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search(SearchArgs a) {
     // stay coalesced and the boundaries of one step fall on consecutive bins.
     // The difference form keeps fewer points in registers (its fold holds more
     // values per boundary).
-    constexpr int UM = DFORM ? 8 : kUMax;
+    constexpr int UM = DFORM ? 4 : kUMax;
     static_assert(UM % kUGroup == 0, "the fold takes whole groups of steps");
     const int nchunks = static_cast<int>((n + static_cast<int64_t>(T) * UM - 1) / (static_cast<int64_t>(T) * UM));
     const int run = static_cast<int>((n + static_cast<int64_t>(T) * nchunks - 1) / (static_cast<int64_t>(T) * nchunks));
@@ -1287,8 +1287,9 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
   BLS_HIP_TRY(hipGetDevice(&dev));
   BLS_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   if (cus < 1) return BLS_E_HIP;
-  // Persistent grid: two workgroups per CU pull items until the counter passes the end.
-  const int64_t grid = std::min<int64_t>(n_items, 2 * static_cast<int64_t>(cus));
+  // Persistent grid: kSearchGroupsPerCu workgroups per CU pull items until the
+  // counter passes the end.
+  const int64_t grid = std::min<int64_t>(n_items, kSearchGroupsPerCu * static_cast<int64_t>(cus));
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);  // 8 counters
   BLS_HIP_TRY(hipGetLastError());
   launch_search(plan->consts.packed != 0, false, a.c.dip_only != 0, grid, st, a);
