@@ -17,15 +17,23 @@ namespace mi355bls {
 
 // Compiled limits.
 constexpr int kThreads = 1024;        // threads per prep / S/N workgroup
-constexpr int kSearchThreads = 512;   // threads per search workgroup; three workgroups per CU
-                                      // (6 waves per SIMD, up to 80 registers per lane)
+constexpr int kSearchThreads = 512;   // threads per search workgroup
+// Two shapes of the one-pass search workgroup.  The common one: 48 KB of
+// per-frequency accumulators, 8 register-resident points per thread and at most 80
+// registers per lane, three workgroups per CU (6 waves per SIMD).  The large one,
+// for frequencies with more fine bins: 72 KB, 12 points, 128 registers, two per CU.
+constexpr int kGBytes = 48 * 1024;
+constexpr int kUMaxSmall = 8;
 constexpr int kSearchGroupsPerCu = 3;
-constexpr int kUMax = 8;              // register-resident points per search thread
-constexpr int kGBytes = 48 * 1024;    // LDS bytes for the per-frequency accumulators (three groups per CU)
-constexpr int kNbLimit = kGBytes / 16 - 32;  // largest fine-bin count searched in one pass:
-                                              // 16 B per bin, plus the replicated wrap bins
+constexpr int kGBytesBig = 72 * 1024;
+constexpr int kUMax = 12;             // register-resident points per thread, at most
+constexpr int kSearchGroupsPerCuBig = 2;
+constexpr int kNbLimit = kGBytes / 16 - 32;        // largest fine-bin count of the common
+                                                    // shape (16 B per bin, plus the
+                                                    // replicated wrap bins): 3040
+constexpr int kNbLimitBig = kGBytesBig / 16 - 32;  // of the large shape: 4576
 constexpr int kNbWide = (1 << 20) - 1;       // largest fine-bin count (window start bins
-                                              // are 20-bit fields); beyond kNbLimit a
+                                              // are 20-bit fields); beyond kNbLimitBig a
                                               // frequency is searched in passes over bin ranges
 constexpr int kFMax = 64;             // most frequencies processed together
 constexpr int kGapLanes = 64;         // stars with more gap points fold in difference form
@@ -117,6 +125,7 @@ struct bls_plan {
   std::vector<double> gap_steps;  // the time step of each entry of gaps
   std::vector<int64_t> freq_offsets;
   int64_t tile_capacity = 0;  // slots of a tiled window list: per star, its tiles + 16
+  bool has_big = false;        // some frequency needs the large workgroup shape
   bool has_wide = false;       // some frequency has more fine bins than one LDS pass holds
   bool has_dform = false;      // some work item has more than kGapLanes gap points
   bool has_dform_star = false; // some star has (caller windows use the star's count)

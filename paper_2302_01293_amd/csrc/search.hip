@@ -252,11 +252,25 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const StarDesc* __restrict
 //   [24K, 48K)  GS  int64 G of the residuals -> FP64 H_S
 // GS sits at a fixed offset from GW, so one address serves each atomic pair.
 // ----------------------------------------------------------------------------
-constexpr int kArrBytes = kGBytes / 2;    // 36 KB per array
 constexpr int kUGroup = 4;                // points whose bins are computed together
-static_assert(kUMax % kUGroup == 0, "the folds take whole groups of steps");
-constexpr int kArrElems = kArrBytes / 8;  // F * stride <= 3072
-constexpr int kSlotIter = kArrElems / kSearchThreads;  // slots per thread (conversion, scan)
+
+// LDS window of a workgroup shape (BIG: the large one).  A group searches the
+// frequencies whose fine-bin count lies in (nb_lo, nb_hi].
+template <bool BIG>
+struct Win {
+  static constexpr int bytes = BIG ? kGBytesBig : kGBytes;
+  static constexpr int arr_bytes = bytes / 2;                // per array (G_W, G_S)
+  static constexpr int elems = arr_bytes / 8;                // F * stride <= elems
+  static constexpr int slot_iter = elems / kSearchThreads;   // slots per thread (scan)
+  static constexpr int nb_lo = BIG ? kNbLimit : 0;
+  static constexpr int nb_hi = BIG ? kNbLimitBig : kNbLimit;
+  static constexpr int groups = BIG ? kSearchGroupsPerCuBig : kSearchGroupsPerCu;
+  static constexpr int um = BIG ? kUMax : kUMaxSmall;        // register points per thread
+};
+static_assert(kUMax % kUGroup == 0 && kUMaxSmall % kUGroup == 0, "the folds take whole groups of steps");
+// A large-shape group holds one frequency (two with more than kNbLimit bins do not
+// fit), so it never reaches frequencies of the common shape.
+static_assert(2 * (kNbLimit + 1) > Win<true>::elems, "one frequency per large-shape group");
 
 struct SearchArgs {
   const StarDesc* stars;
@@ -290,8 +304,12 @@ struct GroupLds {
   double gdt0[kGapCache], gdt1[kGapCache];   // dt of the point before each gap point, and its own
   long long gcw[kGapCache], gcs[kGapCache];  // prefix values at each gap point
 };
-constexpr size_t kSearchLds = kGBytes + sizeof(GroupLds);
-static_assert(kSearchGroupsPerCu * kSearchLds <= 160 * 1024, "search workgroups per CU");
+template <bool BIG>
+constexpr size_t search_lds() {
+  return Win<BIG>::bytes + sizeof(GroupLds);
+}
+static_assert(kSearchGroupsPerCu * search_lds<false>() <= 160 * 1024, "common search workgroups per CU");
+static_assert(kSearchGroupsPerCuBig * search_lds<true>() <= 160 * 1024, "large search workgroups per CU");
 
 __device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int src) {
   const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v)), src));
@@ -353,7 +371,7 @@ constexpr int kTelescope = 0, kDiff = 1;
 
 // One pass of the fold over the wave's block for frequencies k0 and, when TWO,
 // k0 + 1: a point whose bin differs from its predecessor's is a boundary.
-template <bool TWO, bool PACKED, int UM>
+template <bool TWO, bool PACKED, int UM, int ARR>
 __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k0, const GroupLds* g,
                                           const double (&dtr)[UM], const long long (&cwr)[UM],
                                           const long long (&csr)[UM], double dt_before, int run, int form) {
@@ -408,12 +426,12 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
           lds_sub64(smem, o, cwr[u]);
           lds_add64(smem, op, cwr[u]);
           if (!PACKED) {
-            lds_sub64(smem, o + kArrBytes, csr[u]);
-            lds_add64(smem, op + kArrBytes, csr[u]);
+            lds_sub64(smem, o + ARR, csr[u]);
+            lds_add64(smem, op + ARR, csr[u]);
           }
         } else {
           lds_add64(smem, o, cwr[u]);
-          if (!PACKED) lds_add64(smem, o + kArrBytes, csr[u]);
+          if (!PACKED) lds_add64(smem, o + ARR, csr[u]);
         }
       }
       if (TWO) {
@@ -425,12 +443,12 @@ __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k
             lds_sub64(smem, o, cwr[u]);
             lds_add64(smem, op, cwr[u]);
             if (!PACKED) {
-              lds_sub64(smem, o + kArrBytes, csr[u]);
-              lds_add64(smem, op + kArrBytes, csr[u]);
+              lds_sub64(smem, o + ARR, csr[u]);
+              lds_add64(smem, op + ARR, csr[u]);
             }
           } else {
             lds_add64(smem, o, cwr[u]);
-            if (!PACKED) lds_add64(smem, o + kArrBytes, csr[u]);
+            if (!PACKED) lds_add64(smem, o + ARR, csr[u]);
           }
         }
       }
@@ -604,7 +622,7 @@ __device__ __forceinline__ void fold_wide(unsigned char* smem, double f, double 
       if (bb[v] != pa && slot < nslot) {
         const uint32_t o = 8u * static_cast<uint32_t>(slot);
         lds_add64(smem, o, cwr[u]);
-        if (!PACKED) lds_add64(smem, o + kArrBytes, csr[u]);
+        if (!PACKED) lds_add64(smem, o + Win<true>::arr_bytes, csr[u]);
       }
     }
     prev = bb[kUGroup - 1];
@@ -617,9 +635,9 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
                                const int64_t* __restrict__ cw, const int64_t* __restrict__ cs, int nchunks, int run,
                                int64_t chunk_pts, double dt_last) {
   long long* GW = reinterpret_cast<long long*>(smem);
-  long long* GS = reinterpret_cast<long long*>(smem + kArrBytes);
+  long long* GS = reinterpret_cast<long long*>(smem + Win<true>::arr_bytes);
   double* HW = reinterpret_cast<double*>(smem);
-  double* HS = reinterpret_cast<double*>(smem + kArrBytes);
+  double* HS = reinterpret_cast<double*>(smem + Win<true>::arr_bytes);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, T = kSearchThreads;
   const int m_max = a.c.m_max;
   const uint32_t m_mask = a.c.m_mask;
@@ -631,7 +649,7 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
   const double nbd = static_cast<double>(nb);
   const int32_t blast = fold_bin_nc(dt_last, f, nbd);
   const int mlim = min(m_max, nb - 1);
-  const int per_pass = kArrElems - m_max - 1;
+  const int per_pass = Win<true>::elems - m_max - 1;
   // at least two passes, so that nslot < nb and no two slots alias one bin
   const int passes = max(2, (nb + per_pass - 1) / per_pass);
   const int span = (nb + passes - 1) / passes;
@@ -742,10 +760,10 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
       __syncthreads();
     }
     // scan of the windows starting in [b0, b0 + span)
-    unsigned long long skey[kSlotIter];
-    uint32_t smj[kSlotIter];
+    unsigned long long skey[Win<true>::slot_iter];
+    uint32_t smj[Win<true>::slot_iter];
 #pragma unroll
-    for (int r = 0; r < kSlotIter; ++r) {
+    for (int r = 0; r < Win<true>::slot_iter; ++r) {
       const int j = tid + r * T;
       skey[r] = 0ull;
       smj[r] = ~0u;
@@ -776,7 +794,7 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSlotIter; ++r)
+    for (int r = 0; r < Win<true>::slot_iter; ++r)
       if (skey[r] != 0ull && skey[r] == g->key[0]) atomicMin(&g->mj[0], smj[r]);
     __syncthreads();
     if (tid == 0) {
@@ -821,15 +839,17 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
 // DFORM: this launch searches the stars with more than kGapLanes gap points (in
 // difference form) and skips the others; without it, the reverse.  Two kernels
 // keep the register allocation of the common case free of the second form.
-// DIP: only windows with s < 0 (dips) count.
-template <bool PACKED, bool DFORM, bool DIP>
-__global__ void __launch_bounds__(kSearchThreads, 2 * kSearchGroupsPerCu) k_search(SearchArgs a) {
+// DIP: only windows with s < 0 (dips) count.  BIG: the large workgroup shape, for
+// the frequencies whose fine-bin count lies in (kNbLimit, kNbLimitBig].
+template <bool PACKED, bool DFORM, bool DIP, bool BIG>
+__global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search(SearchArgs a) {
+  using W = Win<BIG>;
   extern __shared__ __align__(16) unsigned char smem[];
   long long* GW = reinterpret_cast<long long*>(smem);
-  long long* GS = reinterpret_cast<long long*>(smem + kArrBytes);
+  long long* GS = reinterpret_cast<long long*>(smem + W::arr_bytes);
   double* HW = reinterpret_cast<double*>(smem);
-  double* HS = reinterpret_cast<double*>(smem + kArrBytes);
-  GroupLds* g = reinterpret_cast<GroupLds*>(smem + kGBytes);
+  double* HS = reinterpret_cast<double*>(smem + W::arr_bytes);
+  GroupLds* g = reinterpret_cast<GroupLds*>(smem + W::bytes);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -870,7 +890,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * kSearchGroupsPerCu) k_sear
     // stay coalesced and the boundaries of one step fall on consecutive bins.
     // The difference form keeps fewer points in registers (its fold holds more
     // values per boundary).
-    constexpr int UM = DFORM ? 4 : kUMax;
+    constexpr int UM = DFORM ? (BIG ? 8 : 4) : W::um;
     static_assert(UM % kUGroup == 0, "the fold takes whole groups of steps");
     const int nchunks = static_cast<int>((n + static_cast<int64_t>(T) * UM - 1) / (static_cast<int64_t>(T) * UM));
     const int run = static_cast<int>((n + static_cast<int64_t>(T) * nchunks - 1) / (static_cast<int64_t>(T) * nchunks));
@@ -895,14 +915,15 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * kSearchGroupsPerCu) k_sear
       double f_g;
       int32_t nb_cap;
       grid_point(d, g0, noverlap, f_g, nb_cap);
-      if (nb_cap > kNbLimit) {  // searched by k_search_wide
+      if (nb_cap > W::nb_hi) {  // searched by the large shape or k_search_wide
         F = 1;
         continue;
       }
+      if (BIG && nb_cap <= W::nb_lo) break;  // nb falls with frequency: the rest are the common shape's
       int stride = __builtin_amdgcn_readfirstlane(nb_cap + m_max);
       asm volatile("" : "+s"(stride));
       const float inv_stride = 1.0f / static_cast<float>(stride);
-      F = min(min(kFMax, kArrElems / stride), it.i1 - g0);
+      F = min(min(kFMax, W::elems / stride), it.i1 - g0);
       if (tid < F) {
         double f;
         int32_t nb;
@@ -949,9 +970,9 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * kSearchGroupsPerCu) k_sear
         const double dt_before = dt[wbase > 0 ? wbase - 1 : 0];
         for (int k0 = 0; k0 < F; k0 += 2) {
           if (k0 + 1 < F)
-            fold_pass<true, PACKED, UM>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run, form);
+            fold_pass<true, PACKED, UM, W::arr_bytes>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run, form);
           else
-            fold_pass<false, PACKED, UM>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run, form);
+            fold_pass<false, PACKED, UM, W::arr_bytes>(smem, stride, k0, g, dtr, cwr, csr, dt_before, run, form);
         }
       }
       __syncthreads();
@@ -1052,10 +1073,10 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * kSearchGroupsPerCu) k_sear
       // cross products (no division); the group's best per frequency is then the
       // largest power (an integer maximum on its IEEE bits) and, among slots that
       // reach it, the smallest (m, j).
-      unsigned long long skey[kSlotIter];
-      uint32_t smj[kSlotIter];
+      unsigned long long skey[W::slot_iter];
+      uint32_t smj[W::slot_iter];
 #pragma unroll
-      for (int r = 0; r < kSlotIter; ++r) {
+      for (int r = 0; r < W::slot_iter; ++r) {
         const int idx = tid + r * T;
         int k, j;
         slot_of(idx, stride, inv_stride, k, j);
@@ -1064,7 +1085,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * kSearchGroupsPerCu) k_sear
         if (k < F && j < g->nb[k]) {
           const int32_t nb = g->nb[k];
           const int mlim = min(m_max, nb - 1);
-          // H_S sits kArrElems slots after H_W: one base address for both reads.
+          // H_S sits W::elems slots after H_W: one base address for both reads.
           const double* hwk = HW + idx;
           // Durations ascend, so a strict comparison keeps the smallest m of equal
           // powers within the slot.  Branch-free: every step is read (reads past
@@ -1090,12 +1111,12 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * kSearchGroupsPerCu) k_sear
 #pragma unroll
           for (int m = 1; m <= 12; ++m) {
             rr += hwk[m - 1];
-            ss0 += hwk[kArrElems + m - 1];
+            ss0 += hwk[W::elems + m - 1];
             window(m, rr, ss0);
           }
           for (int m = 13; m <= mlim; ++m) {
             rr += hwk[m - 1];
-            ss0 += hwk[kArrElems + m - 1];
+            ss0 += hwk[W::elems + m - 1];
             window(m, rr, ss0);
           }
           if (bm != 0) {
@@ -1108,7 +1129,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * kSearchGroupsPerCu) k_sear
       }
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < kSlotIter; ++r) {
+      for (int r = 0; r < W::slot_iter; ++r) {
         if (skey[r] != 0ull) {
           int k, j;
           slot_of(tid + r * T, stride, inv_stride, k, j);
@@ -1155,7 +1176,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * kSearchGroupsPerCu) k_sear
 template <bool PACKED>
 __global__ void __launch_bounds__(kSearchThreads, 4) k_search_wide(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  GroupLds* g = reinterpret_cast<GroupLds*>(smem + kGBytes);
+  GroupLds* g = reinterpret_cast<GroupLds*>(smem + Win<true>::bytes);
   const int T = kSearchThreads;
   int queue = static_cast<int>(blockIdx.x % kXcds);  // used by thread 0 only
   int probes = 0;
@@ -1166,7 +1187,7 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search_wide(SearchArgs a)
     double f0;
     int32_t nb0;
     grid_point(d, it.i0, a.c.noverlap, f0, nb0);
-    if (nb0 <= kNbLimit || nb0 > kNbWide) continue;
+    if (nb0 <= kNbLimitBig || nb0 > kNbWide) continue;
     const StarRt rt = a.rt[it.star];
     const double w_unit = PACKED ? packed_w_unit(rt) : 0.0;
     const int64_t n = d.n;
@@ -1181,7 +1202,7 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search_wide(SearchArgs a)
       double f;
       int32_t nb;
       grid_point(d, fi, a.c.noverlap, f, nb);
-      if (nb <= kNbLimit) break;
+      if (nb <= kNbLimitBig) break;
       wide_frequency<PACKED>(smem, g, a, d, rt, fi, w_unit, dt, cw, cs, nchunks, run, chunk_pts, dt_last);
     }
   }
@@ -1234,24 +1255,29 @@ extern "C" bls_status bls_prepare(bls_plan* plan, void* ws, const double* d_t, c
   return BLS_OK;
 }
 
-// The eight instantiations of k_search (packed sums, difference form, dips only).
-static void launch_search(bool packed, bool dform, bool dip, int64_t grid, hipStream_t st, const SearchArgs& a) {
+// The instantiations of k_search for one workgroup shape (packed sums, difference
+// form, dips only), as a persistent grid of `groups` workgroups per CU.
+template <bool BIG>
+static void launch_search(bool packed, bool dform, bool dip, int64_t n_items, int cus, hipStream_t st,
+                          const SearchArgs& a) {
+  const int64_t grid = std::min<int64_t>(n_items, Win<BIG>::groups * static_cast<int64_t>(cus));
   const dim3 gd(static_cast<unsigned>(grid)), bd(kSearchThreads);
+  const size_t lds = search_lds<BIG>();
   if (packed) {
     if (dform) {
-      if (dip) hipLaunchKernelGGL((k_search<true, true, true>), gd, bd, kSearchLds, st, a);
-      else hipLaunchKernelGGL((k_search<true, true, false>), gd, bd, kSearchLds, st, a);
+      if (dip) hipLaunchKernelGGL((k_search<true, true, true, BIG>), gd, bd, lds, st, a);
+      else hipLaunchKernelGGL((k_search<true, true, false, BIG>), gd, bd, lds, st, a);
     } else {
-      if (dip) hipLaunchKernelGGL((k_search<true, false, true>), gd, bd, kSearchLds, st, a);
-      else hipLaunchKernelGGL((k_search<true, false, false>), gd, bd, kSearchLds, st, a);
+      if (dip) hipLaunchKernelGGL((k_search<true, false, true, BIG>), gd, bd, lds, st, a);
+      else hipLaunchKernelGGL((k_search<true, false, false, BIG>), gd, bd, lds, st, a);
     }
   } else {
     if (dform) {
-      if (dip) hipLaunchKernelGGL((k_search<false, true, true>), gd, bd, kSearchLds, st, a);
-      else hipLaunchKernelGGL((k_search<false, true, false>), gd, bd, kSearchLds, st, a);
+      if (dip) hipLaunchKernelGGL((k_search<false, true, true, BIG>), gd, bd, lds, st, a);
+      else hipLaunchKernelGGL((k_search<false, true, false, BIG>), gd, bd, lds, st, a);
     } else {
-      if (dip) hipLaunchKernelGGL((k_search<false, false, true>), gd, bd, kSearchLds, st, a);
-      else hipLaunchKernelGGL((k_search<false, false, false>), gd, bd, kSearchLds, st, a);
+      if (dip) hipLaunchKernelGGL((k_search<false, false, true, BIG>), gd, bd, lds, st, a);
+      else hipLaunchKernelGGL((k_search<false, false, false, BIG>), gd, bd, lds, st, a);
     }
   }
 }
@@ -1287,30 +1313,33 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
   BLS_HIP_TRY(hipGetDevice(&dev));
   BLS_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   if (cus < 1) return BLS_E_HIP;
-  // Persistent grid: kSearchGroupsPerCu workgroups per CU pull items until the
-  // counter passes the end.
-  const int64_t grid = std::min<int64_t>(n_items, kSearchGroupsPerCu * static_cast<int64_t>(cus));
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);  // 8 counters
-  BLS_HIP_TRY(hipGetLastError());
-  launch_search(plan->consts.packed != 0, false, a.c.dip_only != 0, grid, st, a);
-  BLS_HIP_TRY(hipGetLastError());
-  if (d_windows ? plan->has_dform_star : plan->has_dform) {
-    // stars whose steps mostly skip fine bins: a second persistent launch
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);
-    BLS_HIP_TRY(hipGetLastError());
-    launch_search(plan->consts.packed != 0, true, a.c.dip_only != 0, grid, st, a);
-    BLS_HIP_TRY(hipGetLastError());
+  // Persistent launches, each preceded by a reset of the work counters: the common
+  // shape, then (when the batch needs them) stars whose steps mostly skip fine bins
+  // in difference form, the large shape for frequencies with more fine bins, and
+  // the frequencies beyond one LDS pass.  Each launch skips the others' work.
+  const bool packed = plan->consts.packed != 0, dip = a.c.dip_only != 0;
+  const bool dform = d_windows ? plan->has_dform_star : plan->has_dform;
+  for (int big = 0; big < (plan->has_big ? 2 : 1); ++big) {
+    for (int df = 0; df < (dform ? 2 : 1); ++df) {
+      hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);  // 8 counters
+      BLS_HIP_TRY(hipGetLastError());
+      if (big)
+        launch_search<true>(packed, df != 0, dip, n_items, cus, st, a);
+      else
+        launch_search<false>(packed, df != 0, dip, n_items, cus, st, a);
+      BLS_HIP_TRY(hipGetLastError());
+    }
   }
   if (plan->has_wide) {
-    // frequencies with more fine bins than one LDS pass: a second persistent launch
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);
     BLS_HIP_TRY(hipGetLastError());
-    if (plan->consts.packed)
-      hipLaunchKernelGGL(k_search_wide<true>, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads), kSearchLds,
-                         st, a);
+    const int64_t grid = std::min<int64_t>(n_items, kSearchGroupsPerCuBig * static_cast<int64_t>(cus));
+    if (packed)
+      hipLaunchKernelGGL(k_search_wide<true>, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads),
+                         search_lds<true>(), st, a);
     else
       hipLaunchKernelGGL(k_search_wide<false>, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads),
-                         kSearchLds, st, a);
+                         search_lds<true>(), st, a);
   }
   BLS_HIP_TRY(hipGetLastError());
   return BLS_OK;

@@ -157,3 +157,29 @@ def test_streamed_batches_match_single_runs():
         ref = pu.run_gpu(b).results_host()
         assert np.array_equal(r["i_snr"], ref["i_snr"])
         assert np.array_equal(r["snr"].view(np.uint64), ref["snr"].view(np.uint64))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_large_shape_bin_counts(oracle, precision):
+    # six sectors at 200 s of a dense star (rho = 12) searched between 60 and 80 d:
+    # the first frequencies have 3040-3370 fine bins (the large workgroup shape),
+    # the rest fewer (the common shape); few gap points (telescoping form)
+    from paper_2302_01293_amd import _lib
+    t = synth.sector_times(list(range(6)), synth.CADENCE_200S)
+    rng = np.random.default_rng(31)
+    y = 1.0 + rng.normal(0, 1e-3, len(t))
+    y[((t - t[0]) % 71.3) < 0.4] -= 2e-3
+    w = np.full(len(t), 1e6)
+    b = synth.Batch(t, y, w, np.array([0, len(t)]), np.array([12.0]), np.array([60.0]), np.array([80.0]))
+    ds = pu.fetch(pu.run_gpu(b, _lib.default_params(precision=precision)))
+    f, nb = ds.plan.frequencies(0)
+    _say("case large shape: points", len(t), "nb", int(nb[0]), "..", int(nb[-1]), "frequencies", len(f),
+         "precision", precision)
+    assert nb[0] > 3040 >= nb[-1]
+    orc = pu.run_oracle(oracle, b)
+    if precision == 0:
+        pu.compare_star(ds, orc, 0, 0, b.star(0), "large-shape")
+    else:
+        rel = np.abs(ds._sr_host - orc["sr"]) / np.maximum(np.abs(orc["sr"]), 1e-300)
+        _say("large shape packed max rel SR err %.3e" % rel.max())
+        assert rel.max() <= pu.SR_RTOL
