@@ -215,7 +215,7 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
     d.nf = static_cast<int64_t>(steps) + 1;
     d.nb0 = nbins_at(d, 0, p->noverlap);
     if (d.nb0 > kNbWide || d.nb0 < 1) return fail(BLS_E_UNSUPPORTED);
-    if (d.nb0 > kNbLimit) plan->has_big = true;
+    if (d.nb0 > kNbLimit || d.n > kBigPoints) plan->has_big = true;
     if (d.nb0 > kNbLimitBig) plan->has_wide = true;
     const int32_t sturges =
         static_cast<int32_t>(std::floor(1.0 + 3.322 * std::log10(static_cast<double>(d.nf)) + 0.5));

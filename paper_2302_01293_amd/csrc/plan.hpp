@@ -32,6 +32,9 @@ constexpr int kNbLimit = kGBytes / 16 - 32;        // largest fine-bin count of 
                                                     // shape (16 B per bin, plus the
                                                     // replicated wrap bins): 3040
 constexpr int kNbLimitBig = kGBytesBig / 16 - 32;  // of the large shape: 4576
+constexpr int64_t kBigPoints = 100000;  // stars with more points take the large shape
+                                       // for all their frequencies (fewer point
+                                       // re-reads per frequency)
 constexpr int kNbWide = (1 << 20) - 1;       // largest fine-bin count (window start bins
                                               // are 20-bit fields); beyond kNbLimitBig a
                                               // frequency is searched in passes over bin ranges

@@ -268,8 +268,9 @@ struct Win {
   static constexpr int um = BIG ? kUMax : kUMaxSmall;        // register points per thread
 };
 static_assert(kUMax % kUGroup == 0 && kUMaxSmall % kUGroup == 0, "the folds take whole groups of steps");
-// A large-shape group holds one frequency (two with more than kNbLimit bins do not
-// fit), so it never reaches frequencies of the common shape.
+// A large-shape group of a star that is not long holds one frequency (two with
+// more than kNbLimit bins do not fit), so it never reaches frequencies of the
+// common shape.
 static_assert(2 * (kNbLimit + 1) > Win<true>::elems, "one frequency per large-shape group");
 
 struct SearchArgs {
@@ -840,7 +841,8 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
 // difference form) and skips the others; without it, the reverse.  Two kernels
 // keep the register allocation of the common case free of the second form.
 // DIP: only windows with s < 0 (dips) count.  BIG: the large workgroup shape, for
-// the frequencies whose fine-bin count lies in (kNbLimit, kNbLimitBig].
+// the frequencies whose fine-bin count lies in (kNbLimit, kNbLimitBig] and for every
+// frequency up to kNbLimitBig bins of stars with more than kBigPoints points.
 template <bool PACKED, bool DFORM, bool DIP, bool BIG>
 __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search(SearchArgs a) {
   using W = Win<BIG>;
@@ -867,6 +869,10 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
     // Gap points that matter for this item: a prefix of the star's list.
     const int ng = it.n_gaps >= 0 ? it.n_gaps : d.n_gaps;
     if ((ng > kGapLanes) != DFORM) continue;  // the other launch's item
+    // Long stars take the large shape for every frequency; the others only for
+    // frequencies with more fine bins than the common shape holds.
+    const bool long_star = d.n > kBigPoints;
+    if (!BIG && long_star) continue;
     const StarRt rt = a.rt[it.star];
     const double w_unit = PACKED ? packed_w_unit(rt) : 0.0;  // packed: 1 / quantised total weight
     const int64_t n = d.n;
@@ -919,7 +925,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
         F = 1;
         continue;
       }
-      if (BIG && nb_cap <= W::nb_lo) break;  // nb falls with frequency: the rest are the common shape's
+      if (BIG && !long_star && nb_cap <= W::nb_lo) break;  // nb falls with frequency: the rest are the common shape's
       int stride = __builtin_amdgcn_readfirstlane(nb_cap + m_max);
       asm volatile("" : "+s"(stride));
       const float inv_stride = 1.0f / static_cast<float>(stride);

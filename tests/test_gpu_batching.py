@@ -159,13 +159,15 @@ def test_streamed_batches_match_single_runs():
         assert np.array_equal(r["snr"].view(np.uint64), ref["snr"].view(np.uint64))
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_large_shape_bin_counts(oracle, precision):
-    # six sectors at 200 s of a dense star (rho = 12) searched between 60 and 80 d:
-    # the first frequencies have 3040-3370 fine bins (the large workgroup shape),
-    # the rest fewer (the common shape); few gap points (telescoping form)
+@pytest.mark.parametrize("sectors, precision", [(3, 0), (3, 1), (9, 0), (9, 1)])
+def test_large_shape_bin_counts(oracle, sectors, precision):
+    # sectors at 200 s of a dense star (rho = 12) searched between 60 and 80 d: the
+    # first frequencies have 3040-3370 fine bins, the rest fewer; few gap points
+    # (telescoping form).  Three sectors (34,215 points): the large workgroup shape
+    # takes the frequencies above 3040 bins, the common shape the rest; nine sectors
+    # (102,645 points, a long star): the large shape takes every frequency.
     from paper_2302_01293_amd import _lib
-    t = synth.sector_times(list(range(6)), synth.CADENCE_200S)
+    t = synth.sector_times(list(range(sectors)), synth.CADENCE_200S)
     rng = np.random.default_rng(31)
     y = 1.0 + rng.normal(0, 1e-3, len(t))
     y[((t - t[0]) % 71.3) < 0.4] -= 2e-3
@@ -173,8 +175,8 @@ def test_large_shape_bin_counts(oracle, precision):
     b = synth.Batch(t, y, w, np.array([0, len(t)]), np.array([12.0]), np.array([60.0]), np.array([80.0]))
     ds = pu.fetch(pu.run_gpu(b, _lib.default_params(precision=precision)))
     f, nb = ds.plan.frequencies(0)
-    _say("case large shape: points", len(t), "nb", int(nb[0]), "..", int(nb[-1]), "frequencies", len(f),
-         "precision", precision)
+    _say("case large shape: sectors", sectors, "points", len(t), "nb", int(nb[0]), "..", int(nb[-1]),
+         "frequencies", len(f), "precision", precision)
     assert nb[0] > 3040 >= nb[-1]
     orc = pu.run_oracle(oracle, b)
     if precision == 0:
