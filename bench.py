@@ -34,11 +34,13 @@ COUNTERS = os.path.join(ROOT, "profiles", "k_search_cfg1_counters.json")
 
 def search_sources_digest() -> str:
     """Digest of the code (comments and blank lines removed) of the sources that
-    define the search kernel: the counters go stale when it changes."""
+    define the search kernel and its work items: the counters go stale when it
+    changes."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for rel in ("paper_2302_01293_amd/csrc/search.hip", "paper_2302_01293_amd/csrc/plan.hpp"):
+    for rel in ("paper_2302_01293_amd/csrc/search.hip", "paper_2302_01293_amd/csrc/plan.hpp",
+                "paper_2302_01293_amd/csrc/plan.cpp"):
         with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
             text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
         for line in text.splitlines():

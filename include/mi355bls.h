@@ -76,7 +76,8 @@ typedef struct bls_params {
   double a_min_rstar;  /* minimum a/R*: 2 (Sectors 61+) or 3 (Sectors 59-60) */
   double sector_days;  /* gap length that splits continuous stretches (27.4) */
   int64_t tile_cells;  /* target points x frequencies per work item; 0 = library default
-                          (6 Mi); an autotuner may pick another (results do not change) */
+                          (6 Mi cells and at most 128 frequencies per item); an
+                          autotuner may pick another (results do not change) */
 } bls_params;
 
 /* Per-star inputs. */

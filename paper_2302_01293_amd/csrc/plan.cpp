@@ -265,7 +265,9 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
     for (int32_t s = 0; s < n_stars; ++s) {
       const StarDesc& d = plan->stars[s];
       int64_t per = std::max<int64_t>(32, target_cells / std::max<int64_t>(1, d.n));
-      per = std::min<int64_t>(per, 4096);
+      // the default also caps an item at 128 frequencies: short stars then spread
+      // over more items, and the groups working on one XCD share fewer stars' points
+      per = std::min<int64_t>(per, p->tile_cells > 0 ? 4096 : 128);
       plan->stars[s].per_tile = static_cast<int32_t>(per);
       plan->stars[s].tile_off = plan->tile_capacity;
       plan->tile_capacity += (d.nf + per - 1) / per + kWindowSlack;
