@@ -123,7 +123,7 @@ def test_limits():
 
 def test_wide_bin_counts_accepted():
     # a two-year baseline up to 400 d at solar density needs ~4300 fine bins: more
-    # than one LDS pass holds, searched in passes over bin ranges
+    # than the common workgroup shape holds (the large shape searches them)
     t = np.concatenate([synth.sector_times([s], 0.5) for s in range(26)])
     y = np.ones_like(t)
     plan = _lib.Plan(t, y, np.ones_like(t), np.array([0, len(t)]), np.array([1.0]), np.array([50.0]),
