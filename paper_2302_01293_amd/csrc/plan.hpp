@@ -16,7 +16,8 @@
 namespace mi355bls {
 
 // Compiled limits.
-constexpr int kThreads = 1024;        // threads per prep / S/N workgroup
+constexpr int kThreads = 1024;        // threads per preparation / resampling workgroup
+constexpr int kSnrThreads = 256;      // threads per S/N workgroup
 constexpr int kSearchThreads = 512;   // threads per search workgroup
 // Two shapes of the one-pass search workgroup.  The common one: 48 KB of
 // per-frequency accumulators, 8 register-resident points per thread and at most 80

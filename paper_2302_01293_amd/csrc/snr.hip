@@ -9,7 +9,9 @@
 // residual about its median, even counts take the mean of the middle two, first
 // index wins ties of the maximum.
 //
-// One workgroup per star.  Medians are exact order statistics found by an 8-bit
+// One 256-thread workgroup per star (the selections are bound by their barriers,
+// so several small groups per CU beat one large one).  Medians are exact order
+// statistics found by an 8-bit
 // radix select on the FP64 bit patterns (an order-preserving integer key), with
 // the counting done in an LDS histogram.
 #include <hip/hip_runtime.h>
@@ -171,7 +173,7 @@ __device__ void snr_full(const StarDesc& d, const double* __restrict__ sr_all, c
   if (tid == 0) *out = make_result(d, sr, best_all, L, bs.i, bsr.i, bs.v, sigma, status, d.sturges, c.noverlap);
 }
 
-__global__ void __launch_bounds__(kThreads) k_snr(const StarDesc* __restrict__ stars, const double* __restrict__ sr_all,
+__global__ void __launch_bounds__(kSnrThreads) k_snr(const StarDesc* __restrict__ stars, const double* __restrict__ sr_all,
                                                   const bls_best* __restrict__ best_all, double* __restrict__ snr_all,
                                                   double* __restrict__ rho_all, bls_result* __restrict__ res_all,
                                                   Consts c) {
@@ -184,7 +186,7 @@ __global__ void __launch_bounds__(kThreads) k_snr(const StarDesc* __restrict__ s
 // of the same star (a grid with fewer samples per peak), and S/N = (SR - trend) /
 // sigma is evaluated only at the fine frequencies inside the star's windows.  A
 // star flagged for fallback has its full fine spectrum and gets the plain S/N.
-__global__ void __launch_bounds__(kThreads) k_snr_windows(
+__global__ void __launch_bounds__(kSnrThreads) k_snr_windows(
     const StarDesc* __restrict__ fine, const StarDesc* __restrict__ coarse, const double* __restrict__ sr_all,
     const bls_best* __restrict__ best_all, double* __restrict__ rho_fine, const double* __restrict__ sr_coarse_all,
     double* __restrict__ rho_coarse, const int64_t* __restrict__ windows, int32_t per_star,
@@ -238,7 +240,7 @@ extern "C" bls_status bls_snr(bls_plan* plan, void* ws, const double* d_sr, cons
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   const Layout& L = plan->layout;
-  hipLaunchKernelGGL(k_snr, dim3(plan->n_stars), dim3(kThreads), 0, st,
+  hipLaunchKernelGGL(k_snr, dim3(plan->n_stars), dim3(kSnrThreads), 0, st,
                      reinterpret_cast<const StarDesc*>(base + L.stars), d_sr, d_best, d_snr,
                      reinterpret_cast<double*>(base + L.rho), d_result, plan->consts);
   BLS_HIP_TRY(hipGetLastError());
@@ -255,7 +257,7 @@ extern "C" bls_status pp_snr_windows(const bls_plan* fine, void* fine_ws, const 
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* fb = static_cast<char*>(fine_ws);
   char* cb = static_cast<char*>(coarse_ws);
-  hipLaunchKernelGGL(k_snr_windows, dim3(fine->n_stars), dim3(kThreads), 0, st,
+  hipLaunchKernelGGL(k_snr_windows, dim3(fine->n_stars), dim3(kSnrThreads), 0, st,
                      reinterpret_cast<const StarDesc*>(fb + fine->layout.stars),
                      reinterpret_cast<const StarDesc*>(cb + coarse->layout.stars), d_sr, d_best,
                      reinterpret_cast<double*>(fb + fine->layout.rho), d_coarse_sr,
