@@ -17,7 +17,8 @@ namespace mi355bls {
 
 // Compiled limits.
 constexpr int kThreads = 1024;        // threads per preparation / resampling workgroup
-constexpr int kSnrThreads = 256;      // threads per S/N workgroup
+constexpr int kSnrThreads = 256;      // threads per S/N workgroup for short spectra
+constexpr int64_t kSnrSmallMaxFreqs = 32768;  // longest spectrum of such a batch
 constexpr int kSearchThreads = 512;   // threads per search workgroup
 // Two shapes of the one-pass search workgroup.  The common one: 48 KB of
 // per-frequency accumulators, 8 register-resident points per thread and at most 80

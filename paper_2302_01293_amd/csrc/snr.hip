@@ -9,13 +9,15 @@
 // residual about its median, even counts take the mean of the middle two, first
 // index wins ties of the maximum.
 //
-// One 256-thread workgroup per star (the selections are bound by their barriers,
-// so several small groups per CU beat one large one).  Medians are exact order
+// One workgroup per star: 256 threads when every spectrum of the batch is short
+// (the selections are bound by their barriers, so several small groups per CU beat
+// one large one), else 1024.  Medians are exact order
 // statistics found by an 8-bit
 // radix select on the FP64 bit patterns (an order-preserving integer key), with
 // the counting done in an LDS histogram.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -173,7 +175,8 @@ __device__ void snr_full(const StarDesc& d, const double* __restrict__ sr_all, c
   if (tid == 0) *out = make_result(d, sr, best_all, L, bs.i, bsr.i, bs.v, sigma, status, d.sturges, c.noverlap);
 }
 
-__global__ void __launch_bounds__(kSnrThreads) k_snr(const StarDesc* __restrict__ stars, const double* __restrict__ sr_all,
+template <int NT>
+__global__ void __launch_bounds__(NT) k_snr(const StarDesc* __restrict__ stars, const double* __restrict__ sr_all,
                                                   const bls_best* __restrict__ best_all, double* __restrict__ snr_all,
                                                   double* __restrict__ rho_all, bls_result* __restrict__ res_all,
                                                   Consts c) {
@@ -186,7 +189,8 @@ __global__ void __launch_bounds__(kSnrThreads) k_snr(const StarDesc* __restrict_
 // of the same star (a grid with fewer samples per peak), and S/N = (SR - trend) /
 // sigma is evaluated only at the fine frequencies inside the star's windows.  A
 // star flagged for fallback has its full fine spectrum and gets the plain S/N.
-__global__ void __launch_bounds__(kSnrThreads) k_snr_windows(
+template <int NT>
+__global__ void __launch_bounds__(NT) k_snr_windows(
     const StarDesc* __restrict__ fine, const StarDesc* __restrict__ coarse, const double* __restrict__ sr_all,
     const bls_best* __restrict__ best_all, double* __restrict__ rho_fine, const double* __restrict__ sr_coarse_all,
     double* __restrict__ rho_coarse, const int64_t* __restrict__ windows, int32_t per_star,
@@ -233,6 +237,16 @@ __global__ void __launch_bounds__(kSnrThreads) k_snr_windows(
 
 using namespace mi355bls;
 
+namespace {
+// The selections of the S/N step are bound by their barriers: small workgroups (more
+// of them per CU) suit batches of short spectra, large ones long spectra.
+bool snr_small_groups(const bls_plan* plan) {
+  int64_t nf_max = 0;
+  for (const StarDesc& d : plan->stars) nf_max = std::max<int64_t>(nf_max, d.nf);
+  return nf_max <= kSnrSmallMaxFreqs;
+}
+}  // namespace
+
 extern "C" bls_status bls_snr(bls_plan* plan, void* ws, const double* d_sr, const bls_best* d_best,
                               double* d_snr, bls_result* d_result, bls_stream_t stream) {
   if (!plan || !d_sr || !d_result) return BLS_E_ARG;
@@ -240,9 +254,14 @@ extern "C" bls_status bls_snr(bls_plan* plan, void* ws, const double* d_sr, cons
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   const Layout& L = plan->layout;
-  hipLaunchKernelGGL(k_snr, dim3(plan->n_stars), dim3(kSnrThreads), 0, st,
-                     reinterpret_cast<const StarDesc*>(base + L.stars), d_sr, d_best, d_snr,
-                     reinterpret_cast<double*>(base + L.rho), d_result, plan->consts);
+  const StarDesc* sd = reinterpret_cast<const StarDesc*>(base + L.stars);
+  double* rho = reinterpret_cast<double*>(base + L.rho);
+  if (snr_small_groups(plan))
+    hipLaunchKernelGGL(k_snr<kSnrThreads>, dim3(plan->n_stars), dim3(kSnrThreads), 0, st, sd, d_sr, d_best, d_snr,
+                       rho, d_result, plan->consts);
+  else
+    hipLaunchKernelGGL(k_snr<kThreads>, dim3(plan->n_stars), dim3(kThreads), 0, st, sd, d_sr, d_best, d_snr, rho,
+                       d_result, plan->consts);
   BLS_HIP_TRY(hipGetLastError());
   return BLS_OK;
 }
@@ -257,12 +276,16 @@ extern "C" bls_status pp_snr_windows(const bls_plan* fine, void* fine_ws, const 
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* fb = static_cast<char*>(fine_ws);
   char* cb = static_cast<char*>(coarse_ws);
-  hipLaunchKernelGGL(k_snr_windows, dim3(fine->n_stars), dim3(kSnrThreads), 0, st,
-                     reinterpret_cast<const StarDesc*>(fb + fine->layout.stars),
-                     reinterpret_cast<const StarDesc*>(cb + coarse->layout.stars), d_sr, d_best,
-                     reinterpret_cast<double*>(fb + fine->layout.rho), d_coarse_sr,
-                     reinterpret_cast<double*>(cb + coarse->layout.rho), d_windows, windows_per_star, d_fallback,
-                     d_result, fine->consts);
+  const StarDesc* fd = reinterpret_cast<const StarDesc*>(fb + fine->layout.stars);
+  const StarDesc* cd = reinterpret_cast<const StarDesc*>(cb + coarse->layout.stars);
+  double* rf = reinterpret_cast<double*>(fb + fine->layout.rho);
+  double* rc = reinterpret_cast<double*>(cb + coarse->layout.rho);
+  if (snr_small_groups(fine))
+    hipLaunchKernelGGL(k_snr_windows<kSnrThreads>, dim3(fine->n_stars), dim3(kSnrThreads), 0, st, fd, cd, d_sr, d_best,
+                       rf, d_coarse_sr, rc, d_windows, windows_per_star, d_fallback, d_result, fine->consts);
+  else
+    hipLaunchKernelGGL(k_snr_windows<kThreads>, dim3(fine->n_stars), dim3(kThreads), 0, st, fd, cd, d_sr, d_best, rf,
+                       d_coarse_sr, rc, d_windows, windows_per_star, d_fallback, d_result, fine->consts);
   BLS_HIP_TRY(hipGetLastError());
   return BLS_OK;
 }

@@ -203,3 +203,27 @@ def test_gap_point_counts(oracle, precision):
             _say("gaps[%d] packed max rel SR err %.3e" % (s, rel.max()))
             assert rel.max() <= pu.SR_RTOL
             assert int(ds._res_host["i_snr"][s]) == int(orc["results"][s][0])
+
+
+def test_long_spectrum_snr(oracle):
+    # eight sectors at 30-min cadence: 44,634 frequencies, more than the S/N step
+    # serves with its small workgroups (the 1024-thread kernel runs), next to a
+    # one-sector star in the same batch
+    t1 = synth.sector_times(list(range(8)), 1.0 / 48)
+    rng = np.random.default_rng(47)
+    y1 = 1.0 + rng.normal(0, 1e-3, len(t1))
+    y1[((t1 - t1[0]) % 4.7) < 0.15] -= 2.5e-3
+    b0 = synth.config0()
+    t = np.concatenate([t1, b0.t])
+    y = np.concatenate([y1, b0.y])
+    w = np.concatenate([np.full(len(t1), 1e6), b0.w])
+    b = synth.Batch(t, y, w, np.array([0, len(t1), len(t)]), np.array([1.0, b0.rho[0]]), np.array([0.0, b0.pmin[0]]),
+                    np.array([0.0, b0.pmax[0]]))
+    ds = pu.fetch(pu.run_gpu(b))
+    nf = np.diff(ds.plan.freq_offsets)
+    _say("case long spectrum: points", np.diff(b.offsets).tolist(), "frequencies", nf.tolist())
+    assert nf[0] > 32768
+    orc = pu.run_oracle(oracle, b)
+    for s in range(2):
+        st = pu.compare_star(ds, orc, s, s, b.star(s), "long-spectrum[%d]" % s)
+        _say("long-spectrum[%d] max rel SR err %.3e" % (s, st["max_rel_sr"]))
