@@ -244,12 +244,13 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const StarDesc* __restrict
 // ----------------------------------------------------------------------------
 // Fused fold -> boundary accumulation -> H -> duration/phase scan.
 // A persistent grid pulls work items (a frequency range of one star) from a
-// counter; 48 KB of accumulators (plus the group's scalars) per workgroup and at
-// most 80 registers per lane let three workgroups share a CU (six waves per SIMD),
-// so some fold (LDS-atomic bound) while others scan (VALU bound).  LDS layout for
-// the F frequencies of the current group, `stride` slots each (k-major):
-//   [  0, 24K)  GW  int64 G of the weights   -> FP64 H_W
-//   [24K, 48K)  GS  int64 G of the residuals -> FP64 H_S
+// counter.  Common shape: 48 KB of accumulators (plus the group's scalars) per
+// workgroup and at most 80 registers per lane let three workgroups share a CU (six
+// waves per SIMD), so some fold (LDS-atomic bound) while others scan (VALU bound).
+// Large shape: 72 KB and 128 registers, two per CU.  LDS layout for the F
+// frequencies of the current group, `stride` slots each (k-major):
+//   [0, W/2)  GW  int64 G of the weights   -> FP64 H_W
+//   [W/2, W)  GS  int64 G of the residuals -> FP64 H_S     (W = 48 KB or 72 KB)
 // GS sits at a fixed offset from GW, so one address serves each atomic pair.
 // ----------------------------------------------------------------------------
 constexpr int kUGroup = 4;                // points whose bins are computed together
@@ -1176,8 +1177,8 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
   }
 }
 
-// Frequencies with more fine bins than one group's LDS holds; the main kernel
-// skips them.  Same work list; nb falls with frequency, so the wide frequencies of
+// Frequencies with more fine bins than a large-shape group holds (kNbLimitBig);
+// k_search skips them.  Same work list; nb falls with frequency, so the wide frequencies of
 // an item are a prefix of its range.
 template <bool PACKED>
 __global__ void __launch_bounds__(kSearchThreads, 4) k_search_wide(SearchArgs a) {
