@@ -6,7 +6,7 @@ product path never imports it, and it shares no code with the HIP kernels.
 
 The learned proposal is not in the paper (QLP Data Release Notes 003 searches the
 full Keplerian grid of Sec. 2.1); it restricts that grid to a few period windows
-and falls back to the full grid when unsure, so the plain search stays the judge.
+and falls back to the full grid when unsure, so the plain search decides every detection.
 Definitions followed here, in order:
 
 * resample: 4096 uniform bins over the weighted baseline [t0, t_last] (Sec. 2.1

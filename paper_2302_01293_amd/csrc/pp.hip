@@ -6,7 +6,7 @@
 // decides where to search first.  Every window it proposes is searched by the
 // plain BLS kernels, and a star whose proposal is not confident (null probability
 // plus the probability mass inside the windows below a threshold) falls back to
-// its full grid, so BLS stays the judge of every detection.
+// its full grid, so BLS decides every detection.
 //
 // Network (per star): input [2, 4096] BF16 (standardised flux, coverage)
 //   conv1 2->16, kernel 16, stride 2, padding 7, ReLU           -> [16, 2048] BF16
