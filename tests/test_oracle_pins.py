@@ -392,3 +392,51 @@ def test_snr_zero_sigma(oracle):
 def test_median_even_count(oracle):
     assert oracle.median([4.0, 1.0, 3.0, 2.0]) == 2.5
     assert oracle.median([5.0, 1.0, 3.0]) == 3.0
+
+
+def test_best_solution_decode_of_a_physical_box(oracle):
+    """The batch result's period, mid-transit time, duration and depth (Sec. 2.2 item 2
+    takes these as the fit's starting values) recover a box injected by its physical
+    parameters: mid-time T_mid, period P, duration D, depth delta.
+
+    The box is placed so that, at a grid frequency f = 1/P, it covers exactly the fine
+    bins [j0, j0 + m): its mid-time then lies (j0 + m/2)/nb of a period after t0, it lasts
+    m/(nb f) and every in-transit point sits delta below the rest.  The expected values
+    come from the injection, not from the window (a decode from j instead of j + m/2,
+    one that drops t0, or a depth of the wrong sign all fail)."""
+    m_true, depth = 7, 1.5e-3
+    t = synth.sector_times([0], synth.CADENCE_30MIN / 4)
+    pr = dict(pmin=0.5, pmax=13.7)
+    st, bd = oracle.bounds(t, None, 1.0, oracle.params(), **pr)
+    f, nb, _ = oracle.grid(t, None, 1.0, oracle.params(), **pr)
+    i = int(np.argmin(np.abs(1.0 / f - 2.3)))
+    fi, nbi = float(f[i]), int(nb[i])
+    P = 1.0 / fi
+    ph = (t - bd.t0) * fi
+    ph = ph - np.floor(ph)
+    b = np.minimum(nbi - 1, np.floor(ph * nbi).astype(int))
+    for j0 in range(5, nbi - m_true):
+        c = (j0 + 0.5 * m_true) / nbi
+        t_mid = bd.t0 + (3.0 + c) * P              # three periods after the first epoch
+        dur = m_true / (nbi * fi)
+        d = np.mod(t - t_mid + 0.5 * P, P) - 0.5 * P
+        intr = np.abs(d) < 0.5 * dur
+        by_bin = ((b - j0) % nbi) < m_true
+        edge = np.min(np.abs(np.abs(d) - 0.5 * dur))
+        if np.array_equal(intr, by_bin) and edge > 1e-6 and intr.any():
+            break
+    else:
+        pytest.fail("no start bin whose box edges sit clear of the points")
+    y = np.ones_like(t)
+    y[intr] -= depth
+    off = np.array([0, len(t)], np.int64)
+    out = oracle.batch(t, y, np.ones_like(t), off, np.ones(1), np.full(1, pr["pmin"]),
+                       np.full(1, pr["pmax"]))
+    R = dict(zip(oracle.RESULT_FIELDS, out["results"][0]))
+    assert int(R["i_snr"]) == i
+    assert R["period"] == P
+    # first mid-transit time at or after t0: the injected one, three periods earlier
+    assert abs(R["t0"] - (t_mid - 3.0 * P)) <= 1e-11
+    assert abs(R["t0"] - t_mid) > 1.0                 # not the injected epoch itself
+    assert abs(R["duration"] / dur - 1.0) <= 1e-15
+    assert abs(R["depth"] / depth - 1.0) <= 1e-12
