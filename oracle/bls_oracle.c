@@ -249,6 +249,86 @@ typedef struct {
   double* f;    /* [nf] frequencies */
 } orc_spectrum;
 
+/* Normalised inputs of one star (Kovacs): wt = w / W, wx = wt (y - ybar), dt = t - t0. */
+typedef struct {
+  double* wt;
+  double* wx;
+  double* dt;
+  int64_t n;
+} orc_norm;
+
+static int orc_normalise(const double* t, const double* y, const double* w, int64_t n, double t0,
+                         orc_norm* o) {
+  /* The weighted mean must be accurate in absolute terms: the flux level is far
+   * above the signal, and s = sum_in wt (y - ybar) moves by r * (error of ybar).
+   * Both sums therefore use Neumaier's compensated summation. */
+  double W = orc_sum_comp(w, NULL, n);
+  if (!(W > 0.0)) return ORC_E_INPUT;
+  o->n = n;
+  o->wt = (double*)malloc(sizeof(double) * (size_t)n);
+  o->wx = (double*)malloc(sizeof(double) * (size_t)n);
+  o->dt = (double*)malloc(sizeof(double) * (size_t)n);
+  for (int64_t i = 0; i < n; ++i) o->wt[i] = (w ? w[i] : 1.0) / W;
+  double ybar = orc_sum_comp(o->wt, y, n);
+  for (int64_t i = 0; i < n; ++i) {
+    o->wx[i] = o->wt[i] * (y[i] - ybar);
+    o->dt[i] = t[i] - t0;
+  }
+  return ORC_OK;
+}
+
+static void orc_norm_free(orc_norm* o) {
+  free(o->wt);
+  free(o->wx);
+  free(o->dt);
+}
+
+/* Fold, bin and scan at one frequency f with nb fine bins (hw, hs: nb scratch
+ * values each).  Writes SR and the best window (m, j, r, s). */
+static void orc_bls_freq(const orc_norm* d, double f, int32_t nb, const int32_t* mlist, int32_t nm,
+                         int32_t dip_only, double* hw, double* hs, double* sr_out, int32_t* m_out,
+                         int32_t* j_out, double* r_out, double* s_out) {
+  for (int32_t k = 0; k < nb; ++k) hw[k] = hs[k] = 0.0;
+  for (int64_t q = 0; q < d->n; ++q) {
+    double ph = d->dt[q] * f;
+    ph = ph - floor(ph);
+    int32_t bin = (int32_t)floor(ph * (double)nb);
+    if (bin >= nb) bin = nb - 1;
+    hw[bin] += d->wt[q];
+    hs[bin] += d->wx[q];
+  }
+  double best = -1.0, br = 0.0, bs = 0.0;
+  int32_t bm = 0, bj = -1;
+  for (int32_t mi = 0; mi < nm; ++mi) {
+    int32_t m = mlist[mi];
+    /* A window of nb or more bins covers every point (r = 1): never valid. */
+    if (m >= nb) continue;
+    for (int32_t j = 0; j < nb; ++j) {
+      double r = 0.0, s = 0.0;
+      for (int32_t u = 0; u < m; ++u) {
+        int32_t k = (j + u) % nb;
+        r += hw[k];
+        s += hs[k];
+      }
+      if (!(r > 0.0 && r < 1.0)) continue;
+      if (dip_only && !(s < 0.0)) continue;
+      double pw = (s * s) / (r * (1.0 - r));
+      if (pw > best) {
+        best = pw;
+        bm = m;
+        bj = j;
+        br = r;
+        bs = s;
+      }
+    }
+  }
+  *sr_out = best >= 0.0 ? sqrt(best) : 0.0;
+  *m_out = bm;
+  *j_out = bj;
+  *r_out = br;
+  *s_out = bs;
+}
+
 int orc_bls_star(const double* t, const double* y, const double* w, int64_t n, double rho,
                  const orc_params* p, double pmin_override, double pmax_override,
                  orc_spectrum* out, int64_t cap, orc_bounds_t* bounds_out) {
@@ -261,21 +341,9 @@ int orc_bls_star(const double* t, const double* y, const double* w, int64_t n, d
   int32_t mlist[64];
   int32_t nm = orc_durations(p, mlist, 64);
   if (nm <= 0) return ORC_E_ARG;
-
-  /* The weighted mean must be accurate in absolute terms: the flux level is far
-   * above the signal, and s = sum_in wt (y - ybar) moves by r * (error of ybar).
-   * Both sums therefore use Neumaier's compensated summation. */
-  double W = orc_sum_comp(w, NULL, n);
-  if (!(W > 0.0)) return ORC_E_INPUT;
-  double* wt = (double*)malloc(sizeof(double) * (size_t)n);
-  double* wx = (double*)malloc(sizeof(double) * (size_t)n);
-  double* dt = (double*)malloc(sizeof(double) * (size_t)n);
-  for (int64_t i = 0; i < n; ++i) wt[i] = (w ? w[i] : 1.0) / W;
-  double ybar = orc_sum_comp(wt, y, n);
-  for (int64_t i = 0; i < n; ++i) {
-    wx[i] = wt[i] * (y[i] - ybar);
-    dt[i] = t[i] - b.t0;
-  }
+  orc_norm d;
+  st = orc_normalise(t, y, w, n, b.t0, &d);
+  if (st != ORC_OK) return st;
 
   int32_t nb_max = 0;
   for (int64_t i = 0; i < b.nf; ++i) {
@@ -293,51 +361,54 @@ int orc_bls_star(const double* t, const double* y, const double* w, int64_t n, d
     int32_t nb = orc_nbins(&b, p, uu);
     out->f[i] = f;
     out->nb[i] = nb;
-    for (int32_t k = 0; k < nb; ++k) hw[k] = hs[k] = 0.0;
-    for (int64_t q = 0; q < n; ++q) {
-      double ph = dt[q] * f;
-      ph = ph - floor(ph);
-      int32_t bin = (int32_t)floor(ph * (double)nb);
-      if (bin >= nb) bin = nb - 1;
-      hw[bin] += wt[q];
-      hs[bin] += wx[q];
-    }
-    double best = -1.0, br = 0.0, bs = 0.0;
-    int32_t bm = 0, bj = -1;
-    for (int32_t mi = 0; mi < nm; ++mi) {
-      int32_t m = mlist[mi];
-      /* A window of nb or more bins covers every point (r = 1): never valid. */
-      if (m >= nb) continue;
-      for (int32_t j = 0; j < nb; ++j) {
-        double r = 0.0, s = 0.0;
-        for (int32_t u = 0; u < m; ++u) {
-          int32_t k = (j + u) % nb;
-          r += hw[k];
-          s += hs[k];
-        }
-        if (!(r > 0.0 && r < 1.0)) continue;
-        if (p->dip_only && !(s < 0.0)) continue;
-        double pw = (s * s) / (r * (1.0 - r));
-        if (pw > best) {
-          best = pw;
-          bm = m;
-          bj = j;
-          br = r;
-          bs = s;
-        }
-      }
-    }
-    out->sr[i] = best >= 0.0 ? sqrt(best) : 0.0;
-    out->m[i] = bm;
-    out->j[i] = bj;
-    out->r[i] = br;
-    out->s[i] = bs;
+    orc_bls_freq(&d, f, nb, mlist, nm, p->dip_only, hw, hs, out->sr + i, out->m + i, out->j + i,
+                 out->r + i, out->s + i);
   }
   free(hw);
   free(hs);
-  free(wt);
-  free(wx);
-  free(dt);
+  orc_norm_free(&d);
+  return ORC_OK;
+}
+
+/* The same search at a listed subset of the star's grid indices idx[0..k)
+ * (each in [0, nf)); outputs are indexed like idx.  Used to check long
+ * spectra at sampled frequencies and to time the oracle on a bounded sample. */
+int orc_bls_star_at(const double* t, const double* y, const double* w, int64_t n, double rho,
+                    const orc_params* p, double pmin_override, double pmax_override,
+                    const int64_t* idx, int64_t k, orc_spectrum* out, orc_bounds_t* bounds_out) {
+  orc_bounds_t b;
+  int st = orc_bounds(t, w, n, rho, p, pmin_override, pmax_override, &b);
+  if (bounds_out) *bounds_out = b;
+  if (st != ORC_OK) return st;
+  for (int64_t q = 0; q < k; ++q)
+    if (idx[q] < 0 || idx[q] >= b.nf) return ORC_E_ARG;
+  int32_t mlist[64];
+  int32_t nm = orc_durations(p, mlist, 64);
+  if (nm <= 0) return ORC_E_ARG;
+  orc_norm d;
+  st = orc_normalise(t, y, w, n, b.t0, &d);
+  if (st != ORC_OK) return st;
+  int32_t nb_max = 1;
+  for (int64_t q = 0; q < k; ++q) {
+    double uu;
+    (void)orc_freq(&b, idx[q], &uu);
+    int32_t nbi = orc_nbins(&b, p, uu);
+    if (nbi > nb_max) nb_max = nbi;
+  }
+  double* hw = (double*)malloc(sizeof(double) * (size_t)nb_max);
+  double* hs = (double*)malloc(sizeof(double) * (size_t)nb_max);
+  for (int64_t q = 0; q < k; ++q) {
+    double uu;
+    double f = orc_freq(&b, idx[q], &uu);
+    int32_t nb = orc_nbins(&b, p, uu);
+    out->f[q] = f;
+    out->nb[q] = nb;
+    orc_bls_freq(&d, f, nb, mlist, nm, p->dip_only, hw, hs, out->sr + q, out->m + q, out->j + q,
+                 out->r + q, out->s + q);
+  }
+  free(hw);
+  free(hs);
+  orc_norm_free(&d);
   return ORC_OK;
 }
 

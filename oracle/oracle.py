@@ -105,6 +105,9 @@ def lib():
         L.orc_bls_star.restype = ctypes.c_int
         L.orc_bls_star.argtypes = [vp, vp, vp, i64, d, ctypes.POINTER(Params), d, d,
                                    ctypes.POINTER(Spectrum), i64, ctypes.POINTER(Bounds)]
+        L.orc_bls_star_at.restype = ctypes.c_int
+        L.orc_bls_star_at.argtypes = [vp, vp, vp, i64, d, ctypes.POINTER(Params), d, d, vp, i64,
+                                      ctypes.POINTER(Spectrum), ctypes.POINTER(Bounds)]
         L.orc_median.restype = d
         L.orc_median.argtypes = [vp, i64]
         L.orc_sturges.restype = i32
@@ -217,6 +220,24 @@ def bls_star(t, y, w=None, rho=1.0, p: Params | None = None, pmin=0.0, pmax=0.0)
     if st != 0:
         raise ValueError("oracle bls status %d" % st)
     return StarSpectrum(bounds=b2, **arr)
+
+
+def bls_star_at(t, y, w, idx, rho=1.0, p: Params | None = None, pmin=0.0, pmax=0.0) -> StarSpectrum:
+    """The star's BLS at the listed grid indices only (outputs indexed like ``idx``);
+    each frequency is searched exactly as in ``bls_star``."""
+    p = p or params()
+    t, y, w = _f64(t), _f64(y), _f64(w)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    k = len(idx)
+    arr = dict(sr=np.zeros(k), m=np.zeros(k, np.int32), j=np.zeros(k, np.int32),
+               r=np.zeros(k), s=np.zeros(k), nb=np.zeros(k, np.int32), f=np.zeros(k))
+    sp = Spectrum(*[_ptr(arr[n]) for n in ("sr", "m", "j", "r", "s", "nb", "f")])
+    b = Bounds()
+    st = lib().orc_bls_star_at(_ptr(t), _ptr(y), _ptr(w), len(t), rho, ctypes.byref(p), pmin, pmax,
+                               _ptr(idx), k, ctypes.byref(sp), ctypes.byref(b))
+    if st != 0:
+        raise ValueError("oracle bls status %d" % st)
+    return StarSpectrum(bounds=b, **arr)
 
 
 def snr(f, sr, p: Params | None = None):

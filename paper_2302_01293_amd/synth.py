@@ -46,6 +46,7 @@ WORKLOADS = {
     "cfg4": 4,
     "tiny": 5,
     "ragged": 6,
+    "varied": 7,
 }
 
 
@@ -283,6 +284,35 @@ def pp_init_params(seed: int = 0) -> np.ndarray:
     th = np.concatenate([np.asarray(p, np.float64) for p in parts]).astype(np.float32)
     assert th.size == 3122
     return th
+
+
+def varied_weights(n_stars: int = 8, start: int = 0, max_sectors: int = 13, spread: float = 2.0,
+                   cadence: float = CADENCE_200S) -> Batch:
+    """Stars whose points carry their own errors: a span of 1..max_sectors sectors
+    (later sectors present with probability 0.8), a star-level sigma log-uniform in
+    [2e-4, 5e-3] times a per-point factor log-uniform over a range of ``spread``
+    (sigma_n varies by that factor within the star), flux 1 + N(0, sigma_n^2) and
+    weight 1/sigma_n^2, density as config1, and a box in half of the stars."""
+    rows = []
+    for rng in _star_rngs("varied", n_stars, start):
+        sectors = _sector_pattern(rng, max_sectors, 0.8)
+        t = sector_times(sectors, cadence)
+        sig0 = float(np.exp(rng.uniform(np.log(2e-4), np.log(5e-3))))
+        rho = _density(rng)
+        sig = sig0 * np.exp(rng.uniform(-0.5, 0.5, len(t)) * np.log(spread))
+        y = 1.0 + rng.normal(0.0, 1.0, len(t)) * sig
+        inj = bool(rng.uniform() < 0.5)
+        P = epoch = depth = dur = np.nan
+        if inj:
+            hi = min(13.0, 0.25 * (t[-1] - t[0]))
+            P = float(np.exp(rng.uniform(np.log(0.5), np.log(hi))))
+            depth = float(np.exp(rng.uniform(np.log(5e-4), np.log(1e-2))))
+            dur = central_duration(P, rho)
+            epoch = float(t[0] + rng.uniform(0.0, P))
+            y[box_mask(t, P, epoch, dur)] -= depth
+        rows.append((t, y, 1.0 / sig**2, rho, dict(injected=inj, period=P, epoch=epoch, depth=depth,
+                                                   duration=dur, sigma=sig0, n_sectors=len(sectors))))
+    return _collect(rows)
 
 
 def ragged(n_stars: int = 12, start: int = 0, cadence: float = CADENCE_30MIN,

@@ -5,7 +5,7 @@ import math
 import numpy as np
 
 SR_RTOL = 1e-5          # contract: SR within 1e-5 relative of the FP64 oracle
-NEAR_TIE_RTOL = 1e-9    # an (m, j) that differs must be a near-tie of the oracle's power
+NEAR_TIE_RTOL = 1e-12   # an index or (m, j) that differs must be a near-tie of the oracle's values
 
 
 def run_gpu(batch, params=None, want_best=True, want_snr=True):
@@ -40,7 +40,7 @@ def window_power(t, y, w, t0, f, nb, m, j):
 
 def _check_argmax(label, what, i_gpu, i_orc, spec_orc):
     """Best-frequency indices must be equal; the only exception is a near-tie of the
-    oracle's own spectrum (different point sets whose values agree to 1e-9 relative,
+    oracle's own spectrum (different point sets whose values agree to 1e-12 relative,
     where summation order decides), which is reported."""
     if i_gpu == i_orc:
         return
@@ -68,7 +68,9 @@ def compare_star(ds, orc, s_gpu, s_orc, batch_star, label=""):
         bg = ds._best_host[sl]
         mm = np.nonzero((bg["m"] != orc["m"][o0:o1]) | (bg["j"] != orc["j"][o0:o1]))[0]
         t, y, w = batch_star
-        for i in mm[:20]:
+        if len(mm):
+            print("%s: %d best windows differ; each must be a near-tie" % (label, len(mm)), flush=True)
+        for i in mm:
             f, nb = orc["f"][o0 + i], orc["nb"][o0 + i]
             t0 = t[np.nonzero(w > 0)[0][0]]
             pg = window_power(t, y, w, t0, f, nb, bg["m"][i], bg["j"][i])
@@ -76,7 +78,6 @@ def compare_star(ds, orc, s_gpu, s_orc, batch_star, label=""):
             assert abs(pg - po) <= NEAR_TIE_RTOL * max(abs(po), 1e-300), \
                 "%s: window differs at %d: gpu (%d,%d) %.17g vs oracle (%d,%d) %.17g" % (
                     label, i, bg["m"][i], bg["j"][i], pg, orc["m"][o0 + i], orc["j"][o0 + i], po)
-        assert len(mm) <= max(2, len(sr_o) // 1000), "%s: %d windows differ" % (label, len(mm))
         ok = (bg["j"] >= 0) & (orc["j"][o0:o1] >= 0) & (bg["m"] == orc["m"][o0:o1]) & (bg["j"] == orc["j"][o0:o1])
         if ok.any():
             np.testing.assert_allclose(bg["r"][ok], orc["r"][o0:o1][ok], rtol=1e-9, atol=1e-15)

@@ -440,3 +440,16 @@ def test_best_solution_decode_of_a_physical_box(oracle):
     assert abs(R["t0"] - t_mid) > 1.0                 # not the injected epoch itself
     assert abs(R["duration"] / dur - 1.0) <= 1e-15
     assert abs(R["depth"] / depth - 1.0) <= 1e-12
+
+
+def test_sampled_frequencies_equal_the_full_search(oracle):
+    # The sampled form runs the same per-frequency search: bit-equal outputs.
+    b = synth.ragged(2, start=3)
+    t, y, w = b.star(1)
+    full = oracle.bls_star(t, y, w, float(b.rho[1]))
+    idx = np.array([0, 7, len(full.sr) // 2, len(full.sr) - 1, 7])
+    part = oracle.bls_star_at(t, y, w, idx, float(b.rho[1]))
+    for k in ("sr", "m", "j", "r", "s", "nb", "f"):
+        assert np.array_equal(getattr(part, k), getattr(full, k)[idx]), k
+    with pytest.raises(ValueError):
+        oracle.bls_star_at(t, y, w, [len(full.sr)], float(b.rho[1]))
