@@ -1,18 +1,26 @@
 """Benchmark of the MI355X BLS + S/N hot path.
 
-One step = the whole path over one batch resident in HBM: bls_prepare (normalise,
-fixed-point prefix sums) -> bls_search_batch (fold, boundary accumulation, duration/
-phase scan) -> bls_snr (Sturges median-binned trend, MAD sigma, argmax).
+One step = the whole path over one batch of stars whose light curves are already
+resident in HBM: the host plan (C++: bounds, Keplerian grid, work items; built
+while the previous step runs on the GPU), the descriptor upload, bls_prepare
+(normalise, fixed-point prefix sums), bls_search_batch (fold, boundary
+accumulation, duration/phase scan), bls_snr (Sturges median-binned trend, MAD
+sigma, argmax) and the copy of the per-star results back to the host.
 
-Default workload: 4096 synthetic one-sector stars at 200-s cadence (11,405 points
-each), per-star Keplerian grids (Pmin at a = 2 R*, Pmax from the data), plain
-FP64-phase path.  Prints ONE JSON line on stdout; progress goes to stderr.
+Default workload: the sector-scale mix -- every step is a new batch of 256 stars
+of 1-26 contiguous TESS sectors at 200-s cadence (11k-297k points, up to ~2 yr
+baselines, periods up to half the longest stretch, 10% injected boxes), per-star
+Keplerian grids (Pmin at a = 2 R*), plain FP64-phase path with exact bin sums.
+``--workload cfg1`` (4096 one-sector stars, the same batch every step) and
+``cfg2`` / ``cfg0`` remain available.  Prints ONE JSON line on stdout; progress
+goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -29,7 +37,8 @@ FP64_OPS_PEAK = 256 * 64 * 2.4e9
 OPS_PER_CELL = 4  # DMUL (dt f), FRACT, DMUL (phase nb), CVT (bin index)
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "k_search_cfg1_counters.json")
+def counters_path(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", "k_search_%s_counters.json" % workload)
 
 
 def search_sources_digest() -> str:
@@ -50,16 +59,16 @@ def search_sources_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per k_search launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs (scaled by a plain copy's readings), if they were taken on this
-    workload with the current kernel sources; else None."""
+def measured_traffic(workload: str, key: dict):
+    """HBM bytes per search call from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    runs (scaled by a plain copy's readings), if they were taken on this workload
+    (same batch shape) with the current kernel sources; else None."""
     try:
-        with open(COUNTERS) as fh:
+        with open(counters_path(workload)) as fh:
             c = json.load(fh)
     except (OSError, ValueError):
         return None
-    if c.get("workload") != workload or c.get("source_sha256") != search_sources_digest():
+    if c.get("source_sha256") != search_sources_digest() or c.get("key") != key:
         return None
     return float(c["bytes_per_launch"])
 
@@ -68,45 +77,125 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_workload(name: str, n_stars: int = 0):
+def _threads() -> int:
+    """Host threads for generation and the CPU baseline: the process's CPU share
+    (affinity), capped by OMP_NUM_THREADS when it is set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def make_workload(name: str, n_stars: int, batch_stars: int, steps: int):
+    """List of batches (one per step for the sector-scale mix; one shared batch
+    otherwise) and a description."""
+    from concurrent.futures import ThreadPoolExecutor
+
     from paper_2302_01293_amd import synth
     if name == "cfg0":
-        return synth.config0(), "1 star, 27.4 d at 30-min cadence, P 0.5-13.7 d, plain FP64"
+        return [synth.config0()], "1 star, 27.4 d at 30-min cadence, P 0.5-13.7 d, plain FP64"
     if name == "cfg1":
-        return synth.config1(), "4096 stars x 1 sector at 200 s (11,405 pts), Pmin a=2R*, plain FP64"
+        b = synth.config1(n_stars or 4096)
+        return [b], "%d stars x 1 sector at 200 s (11,405 pts), Pmin a=2R*, plain FP64" % b.n_stars
     if name == "cfg2":
         n = n_stars or 16384
-        return synth.config2(n), "%d stars, 1-13 sectors at 200 s (uneven, missing sectors)" % n
+        return [synth.config2(n)], "%d stars, 1-13 sectors at 200 s (uneven, missing sectors)" % n
+    if name == "cfg4":
+        B = batch_stars
+
+        def gen(k):
+            return synth.config4(B, start=k * B)
+
+        total = B * steps
+        with ThreadPoolExecutor(_threads()) as ex:
+            batches = list(ex.map(gen, range(steps)))
+        return batches, ("sector-scale mix: %d new stars per step (%d in all), 1-26 contiguous sectors "
+                         "at 200 s (11k-297k pts), 10%% boxes, Pmin a=2R*, plain FP64" % (B, total))
     raise SystemExit("unknown workload %s" % name)
 
 
-def cpu_baseline(batch, n_sample: int, seed: int = 7):
-    """The oracle as it stands, on a bounded random sample of the same workload."""
+def cpu_baseline_cells(batches, stride: int, cells_per_star: float):
+    """The oracle as it stands on a bounded sample of the benchmark's stars: one star
+    per sector count (stratified), every ``stride``-th frequency of its grid (each
+    frequency searched in full: fold, bins, every window).  Throughput in cells/s
+    is extrapolated to stars/hour with the workload's mean cells per star."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import oracle
+    seen = {}
+    for bi, b in enumerate(batches):
+        for s in range(b.n_stars):
+            k = int(b.truth["n_sectors"][s])
+            if k not in seen:
+                seen[k] = (bi, s)
+    picks = [seen[k] for k in sorted(seen)]
+    jobs = []
+    for bi, s in picks:
+        b = batches[bi]
+        t, y, w = b.star(s)
+        st, bd = oracle.bounds(t, w, float(b.rho[s]))
+        idx = np.arange(0, bd.nf, stride, dtype=np.int64)
+        jobs.append((t, y, w, float(b.rho[s]), idx, len(t) * len(idx)))
+    cores = _threads()
+
+    def run(j):
+        t, y, w, rho, idx, _ = j
+        oracle.bls_star_at(t, y, w, idx, rho)
+
+    oracle.lib()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        list(ex.map(run, sorted(jobs, key=lambda j: -j[5])))
+    dt = time.perf_counter() - t0
+    cells = float(sum(j[5] for j in jobs))
+    cps = cells / dt
+    return dict(value=cps / cells_per_star * 3600.0, unit="stars/hour", cores=cores, kind="oracle",
+                sample=("%d stars of the workload (one per sector count %d-%d), 1 in %d grid frequencies "
+                        "of each: %.3g cells in %.1f s = %.3g cells/s, extrapolated with the workload's "
+                        "%.3g cells per star (the S/N step, O(N_f log N_f), is not timed)"
+                        % (len(jobs), min(seen), max(seen), stride, cells, dt, cps, cells_per_star)),
+                cells_per_s=cps, nproc=os.cpu_count(), cpu_model=cpu_model(),
+                single_core_s_per_star=cells_per_star / (cps / cores))
+
+
+def cpu_baseline_full(batch, n_sample: int, seed: int = 7):
+    """The oracle as it stands on a bounded random sample of whole stars."""
     from oracle import oracle
     rng = np.random.default_rng(seed)
     S = batch.n_stars
     sample = np.sort(rng.choice(S, size=min(n_sample, S), replace=False))
-    cores = max(1, min(16, os.cpu_count() or 1))
+    cores = _threads()
     t0 = time.perf_counter()
     oracle.batch(batch.t, batch.y, batch.w, batch.offsets, batch.rho, batch.pmin, batch.pmax,
                  stars=sample, nthreads=cores)
     dt = time.perf_counter() - t0
     return dict(value=len(sample) / dt * 3600.0, unit="stars/hour", cores=cores, kind="oracle",
                 sample="%d random stars of the %d-star workload, full spectrum + S/N each (%.1f s)"
-                       % (len(sample), S, dt))
+                       % (len(sample), S, dt), nproc=os.cpu_count(), cpu_model=cpu_model())
 
 
-def learned_vs_plain(batch, conf: float, topk: int):
-    """Recovery of the plain detections and device-time ratio of the learned path
-    (committed trained weights) on the benchmark's own stars."""
-    from paper_2302_01293_amd import learned
-    path = os.path.join(ROOT, "paper_2302_01293_amd", "pp_weights.npy")
-    net = learned.ProposalNet(np.load(path))
-    r, _, _ = learned.time_paths(batch, net, reps=3, conf=conf, topk=topk)
-    r.update(conf=conf, topk=topk, weights="paper_2302_01293_amd/pp_weights.npy")
-    log("learned: recovery %d/%d, speed-up %.2fx, fallback %.3f, searched %.3f" % (
-        r["recovered"], r["plain_detections"], r["speedup"], r["fallback_fraction"], r["searched_fraction"]))
-    return r
+class Step:
+    """One batch on the device: input tensors, plan, and the per-step buffers."""
+
+    def __init__(self, batch, dev):
+        import torch
+        self.batch = batch
+        self.t = torch.as_tensor(batch.t).to(dev)
+        self.y = torch.as_tensor(batch.y).to(dev)
+        self.w = torch.as_tensor(batch.w).to(dev)
+        self.plan = None
 
 
 def main():
@@ -114,16 +203,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg1")
-    ap.add_argument("--stars", type=int, default=0, help="use only the first N stars of the workload")
+    ap.add_argument("--workload", default="cfg4")
+    ap.add_argument("--stars", type=int, default=0, help="cfg1/cfg2: number of stars")
+    ap.add_argument("--batch-stars", type=int, default=256, help="cfg4: new stars per step")
     ap.add_argument("--precision", type=int, default=0,
                     help="0: exact int64 bin sums (plain FP64 path); 1: packed reduced-precision sums")
-    ap.add_argument("--cpu-sample", type=int, default=768)
+    ap.add_argument("--cpu-sample", type=int, default=768, help="cfg1/cfg2: whole stars timed on the CPU")
+    ap.add_argument("--cpu-stride", type=int, default=32,
+                    help="cfg4: the CPU baseline searches every n-th frequency of its sample stars")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-proposal comparison (trained weights vs the plain path)")
-    ap.add_argument("--learned-conf", type=float, default=0.95)
-    ap.add_argument("--learned-topk", type=int, default=12)
+    ap.add_argument("--learned-batches", type=int, default=8,
+                    help="cfg4: steps' batches on which the learned path is compared with the plain one")
+    ap.add_argument("--learned-points", default="0.9:8,0.95:12",
+                    help="confidence:top-k operating points of the learned path")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size kernel "
                          "for scaling the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -134,12 +228,13 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2302_01293_amd.device import DeviceSearch
+    from paper_2302_01293_amd import _lib
 
     assert torch.cuda.is_available(), "no GPU"
+    dev = torch.device("cuda")
     if args.copy_calibration_mib:
         nel = args.copy_calibration_mib * (1 << 20) // 8
-        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
@@ -147,57 +242,113 @@ def main():
         log("copy calibration: %d MiB read + %d MiB written" % (args.copy_calibration_mib,
                                                                   args.copy_calibration_mib))
         del src, dst
+    t_gen = time.perf_counter()
     log("generating workload", args.workload)
-    batch, desc = make_workload(args.workload, args.stars if args.workload == "cfg2" else 0)
-    if args.stars and args.stars < batch.n_stars:
-        batch = batch.subset(np.arange(args.stars))
-        desc += " (first %d stars)" % args.stars
-    log("stars", batch.n_stars, "points", batch.n_points)
-    from paper_2302_01293_amd import _lib
-    ds = DeviceSearch.from_batch(batch, _lib.default_params(precision=args.precision))
+    batches, desc = make_workload(args.workload, args.stars, args.batch_stars, args.steps)
+    log("generated %d batch(es), %d stars, %d points (%.1f s)" % (
+        len(batches), sum(b.n_stars for b in batches), sum(b.n_points for b in batches),
+        time.perf_counter() - t_gen))
+    params = _lib.default_params(precision=args.precision)
     if args.precision:
         desc += ", packed reduced-precision sums"
-    nfs = np.diff(ds.plan.freq_offsets)
-    npts = np.diff(batch.offsets)
-    cells = float(np.sum(nfs.astype(np.float64) * npts))
-    log("frequencies", int(nfs.sum()), "cells %.3e" % cells)
 
+    # Every batch's light curves go to HBM before the clock starts.
+    steps = [Step(b, dev) for b in batches]
+    # Per-step sizes (the plans are built again inside the timed loop for a new batch).
+    sizes = []
+    for st in steps:
+        pl = _lib.Plan(st.batch.t, st.batch.y, st.batch.w, st.batch.offsets, st.batch.rho,
+                       st.batch.pmin, st.batch.pmax, params)
+        nfs = np.diff(pl.freq_offsets)
+        sizes.append(dict(nf=int(pl.n_freq), ws=int(pl.workspace_bytes),
+                          cells=float(np.sum(nfs.astype(np.float64) * np.diff(st.batch.offsets)))))
+        if len(steps) == 1:
+            st.plan = pl
+        else:
+            pl.close()
+    ws_bytes = max(s["ws"] for s in sizes)
+    nf_max = max(s["nf"] for s in sizes)
+    s_max = max(b.n_stars for b in batches)
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+    ws_ptr = (ws.data_ptr() + 255) // 256 * 256
+    sr = torch.empty(nf_max, dtype=torch.float64, device=dev)
+    best = torch.empty(nf_max * _lib.BEST_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    res_dev = torch.empty(s_max * _lib.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        ds.run()
+    h = int(stream.cuda_stream)
+    n_batches = len(steps)
+    log("per-step batch: %.3g cells on average, %d frequencies at most, workspace %.2f GB"
+        % (np.mean([s["cells"] for s in sizes]), nf_max, ws_bytes / 1e9))
+
+    def run_step(k, ev=None, res_host=None):
+        st = steps[k % n_batches]
+        b = st.batch
+        if n_batches > 1 or st.plan is None:
+            st.plan = _lib.Plan(b.t, b.y, b.w, b.offsets, b.rho, b.pmin, b.pmax, params)
+        pl = st.plan
+        if ev is not None:
+            ev[0].record(stream)
+        pl.upload(ws_ptr, ws_bytes, h)
+        pl.prepare(ws_ptr, st.t.data_ptr(), st.y.data_ptr(), st.w.data_ptr(), h)
+        if ev is not None:
+            ev[1].record(stream)
+        pl.search(ws_ptr, sr.data_ptr(), best.data_ptr(), None, 0, h)
+        if ev is not None:
+            ev[2].record(stream)
+        pl.snr(ws_ptr, sr.data_ptr(), best.data_ptr(), None, res_dev.data_ptr(), h)
+        if ev is not None:
+            ev[3].record(stream)
+        if res_host is not None:
+            res_host.copy_(res_dev[:b.n_stars * _lib.RESULT_DTYPE.itemsize], non_blocking=True)
+        return pl
+
+    keep = []
+    for k in range(args.warmup):
+        keep.append(run_step(k))
+        keep = keep[-2:]
     torch.cuda.synchronize()
-    log("warmup done")
+    log("warmup done (%d steps)" % args.warmup)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    res_host = [torch.empty(steps[k % n_batches].batch.n_stars * _lib.RESULT_DTYPE.itemsize,
+                            dtype=torch.uint8, pin_memory=True) for k in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
-        e = ev[k]
-        e[0].record(stream)
-        ds.run_prepare()
-        e[1].record(stream)
-        ds.run_search()
-        e[2].record(stream)
-        ds.run_snr()
-        e[3].record(stream)
+        keep.append(run_step(k, ev[k], res_host[k]))
+        keep = keep[-2:]          # a plan's host descriptors stay alive while its copy may run
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    prep = np.mean([ev[k][0].elapsed_time(ev[k][1]) for k in range(args.steps)])
-    srch = np.mean([ev[k][1].elapsed_time(ev[k][2]) for k in range(args.steps)])
-    snr = np.mean([ev[k][2].elapsed_time(ev[k][3]) for k in range(args.steps)])
-    step_ms = np.mean([ev[k][0].elapsed_time(ev[k][3]) for k in range(args.steps)])
-    log("per step ms: prepare %.3f search %.3f snr %.3f total %.3f (wall/step %.3f)"
-        % (prep, srch, snr, step_ms, wall * 1e3 / args.steps))
-    res = ds.results_host()
-    inj = np.asarray(batch.truth.get("injected", np.zeros(batch.n_stars, bool)), bool)
-    if inj.any():
-        hit = np.abs(res["period"][inj] / np.asarray(batch.truth["period"])[inj] - 1) < 0.01
-        log("injections recovered at the best-S/N period: %d / %d" % (hit.sum(), inj.sum()))
+    del keep
+    prep = np.array([ev[k][0].elapsed_time(ev[k][1]) for k in range(args.steps)])
+    srch = np.array([ev[k][1].elapsed_time(ev[k][2]) for k in range(args.steps)])
+    snr = np.array([ev[k][2].elapsed_time(ev[k][3]) for k in range(args.steps)])
+    dev_ms = np.array([ev[k][0].elapsed_time(ev[k][3]) for k in range(args.steps)])
+    step_ms = wall * 1e3 / args.steps
+    n_timed = sum(steps[k % n_batches].batch.n_stars for k in range(args.steps))
+    cells = float(sum(sizes[k % n_batches]["cells"] for k in range(args.steps)))
+    log("per step ms (device): prepare %.3f search %.3f snr %.3f total %.3f; wall/step %.3f"
+        % (prep.mean(), srch.mean(), snr.mean(), dev_ms.mean(), step_ms))
+    results = [res_host[k].numpy().view(_lib.RESULT_DTYPE).copy() for k in range(args.steps)]
+    n_inj = n_hit = 0
+    for k in range(args.steps):
+        b = steps[k % n_batches].batch
+        inj = np.asarray(b.truth.get("injected", np.zeros(b.n_stars, bool)), bool)
+        if inj.any():
+            p = results[k]["period"][inj]
+            pt = np.asarray(b.truth["period"])[inj]
+            n_hit += int(np.sum(np.abs(p / pt - 1) < 0.01))
+            n_inj += int(inj.sum())
+    log("injections recovered at the best-S/N period: %d / %d" % (n_hit, n_inj))
 
-    achieved = OPS_PER_CELL * cells / (srch * 1e-3) / 1e12
+    search_s = float(srch.sum()) * 1e-3
+    achieved = OPS_PER_CELL * cells / search_s / 1e12
     peak = FP64_OPS_PEAK / 1e12
+    key = dict(workload=args.workload, batch_stars=args.batch_stars if args.workload == "cfg4" else None,
+               stars=args.stars or None, precision=args.precision)
+    traffic = measured_traffic(args.workload, key)
     out = {
         "metric": METRIC,
-        "value": batch.n_stars / (step_ms * 1e-3) * 3600.0,
+        "value": n_timed / (wall) * 3600.0,
         "unit": "stars/hour",
         "n_gpus": 1,
         "steps": args.steps,
@@ -208,22 +359,88 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload + ": " + desc, "stars": batch.n_stars,
-                   "points": batch.n_points, "frequencies": int(nfs.sum()), "cells": cells},
-        "cells_per_s": cells / (srch * 1e-3),
-        "kernel_ms": {"prepare": prep, "search": srch, "snr": snr},
+        "config": {"workload": args.workload + ": " + desc, "stars_timed": n_timed,
+                   "points_timed": int(sum(steps[k % n_batches].batch.n_points for k in range(args.steps))),
+                   "frequencies_timed": int(sum(sizes[k % n_batches]["nf"] for k in range(args.steps))),
+                   "cells_timed": cells},
+        "cells_per_s": cells / search_s,
+        "cells_per_s_end_to_end": cells / wall,
+        "kernel_ms_per_step": {"prepare": float(prep.mean()), "search": float(srch.mean()),
+                               "snr": float(snr.mean()), "device_total": float(dev_ms.mean())},
+        "injections_recovered": [n_hit, n_inj],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak,
-                     "traffic": measured_traffic(args.workload) if not (args.stars or args.precision) else None,
-                     "kernel": "k_search (fold + boundary accumulation + scan)"},
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "k_search (fold + boundary accumulation + scan; all launches of "
+                               "bls_search_batch)"},
     }
     if not args.no_learned:
-        log("learned proposal vs plain on the same stars ...")
-        out["learned"] = learned_vs_plain(batch, args.learned_conf, args.learned_topk)
+        out["learned"] = learned_vs_plain(args, steps, results, dev_ms, params)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) on a sample ...")
-        out["cpu_baseline"] = cpu_baseline(batch, args.cpu_sample)
+        if args.workload == "cfg4":
+            out["cpu_baseline"] = cpu_baseline_cells([s.batch for s in steps], args.cpu_stride,
+                                                     cells / n_timed)
+        else:
+            out["cpu_baseline"] = cpu_baseline_full(batches[0], args.cpu_sample)
+        log("cpu baseline: %.4g stars/hour" % out["cpu_baseline"]["value"])
     print(json.dumps(out), flush=True)
+
+
+def learned_vs_plain(args, steps, plain_results, plain_ms, params):
+    """Recovery of the plain detections and device-time ratio of the learned path
+    (committed trained weights) on the benchmark's own stars: the plain results and
+    device times are those of the timed steps."""
+    import torch
+
+    from paper_2302_01293_amd import learned
+    path = os.path.join(ROOT, "paper_2302_01293_amd", "pp_weights.npy")
+    net = learned.ProposalNet(np.load(path))
+    nb = min(args.learned_batches, args.steps) if len(steps) > 1 else 1
+    stream = torch.cuda.current_stream()
+    out = dict(weights="paper_2302_01293_amd/pp_weights.npy", batches=nb,
+               stars=int(sum(steps[k].batch.n_stars for k in range(nb))), points=[])
+    for spec in args.learned_points.split(","):
+        conf, topk = spec.split(":")
+        conf, topk = float(conf), int(topk)
+        t_l = t_p = 0.0
+        agg = dict(plain_detections=0, recovered=0, exact_index=0)
+        fb = searched = nf_all = 0.0
+        conf_stats = dict(confident_detections=0, confident_recovered=0)
+        for k in range(nb):
+            b = steps[k].batch
+            ls = learned.LearnedSearch(b, net, params=params, topk=topk, conf=conf)
+            ls.run()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ls.run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t_l += e0.elapsed_time(e1)
+            t_p += float(plain_ms[k])
+            lres = ls.fine.results_host()
+            r = learned.recovery(plain_results[k], lres, b.truth)
+            for q in agg:
+                agg[q] += r[q]
+            f = ls.fallback.cpu().numpy().astype(bool)
+            rc = learned.recovery(plain_results[k][~f], lres[~f],
+                                  {q: np.asarray(v)[~f] for q, v in b.truth.items()})
+            conf_stats["confident_detections"] += rc["plain_detections"]
+            conf_stats["confident_recovered"] += rc["recovered"]
+            fb += float(f.sum())
+            searched += ls.searched_fraction() * ls.fine.plan.n_freq
+            nf_all += ls.fine.plan.n_freq
+            del ls
+        n_stars = out["stars"]
+        pt = dict(conf=conf, topk=topk, plain_ms=t_p, learned_ms=t_l, speedup=t_p / t_l,
+                  fallback_fraction=fb / n_stars, recovery=agg["recovered"] / max(agg["plain_detections"], 1),
+                  **agg, **conf_stats)
+        pt["searched_fraction"] = searched / nf_all
+        log("learned conf %.2f top-%d: recovery %d/%d (confident stars %d/%d), speed-up %.2fx, fallback %.3f"
+            % (conf, topk, agg["recovered"], agg["plain_detections"], conf_stats["confident_recovered"],
+               conf_stats["confident_detections"], pt["speedup"], pt["fallback_fraction"]))
+        out["points"].append(pt)
+    return out
 
 
 if __name__ == "__main__":

@@ -125,9 +125,12 @@ def test_backward_parity():
     assert abs(loss - lo) <= 1e-3 * abs(lo)
     for name, (a, b_) in P.OFF.items():
         ga, gb = g[a:b_], go[a:b_]
-        err = np.linalg.norm(ga - gb) / max(np.linalg.norm(gb), 1e-12)
-        _say("grad %-5s rel L2 err %.2e (norm %.3e)" % (name, err, np.linalg.norm(gb)))
-        assert err <= 2e-2, name
+        scale = max(float(np.max(np.abs(gb))), 1e-12)
+        err = np.abs(ga - gb) / scale
+        _say("grad %-5s element-wise: max |gpu - oracle| / max|oracle| %.2e, elements above 1e-5: %d of %d"
+             % (name, err.max(), int(np.sum(err > 1e-5)), len(err)))
+        # every element, not a norm: a wrong tap anywhere in a group fails
+        assert err.max() <= 1e-4, name
     # deterministic: same gradient bits on a second evaluation
     g1 = net.grad.clone()
     net.gradient(xd, ld, tgt)
