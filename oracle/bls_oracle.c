@@ -605,6 +605,73 @@ int orc_batch_run(int32_t S, const int64_t* offsets, const double* t, const doub
   return err ? ORC_E_INPUT : ORC_OK;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Other statistics of the detection (Sec. 2.2 item 5) and the detection     */
+/* criteria (the paragraph after the list), at the best window of one       */
+/* frequency f with nb fine bins: duration m bins starting at bin j.         */
+/* Only points with w > 0 count as data.  With p = (t - t0) f, its integer   */
+/* part ip and bin b = min(nb - 1, floor((p - ip) nb)) (the search's fold),  */
+/* o = (b - j) mod nb places a point relative to the window:                 */
+/*   in transit      o < m                (within half a duration of the    */
+/*                                          mid-transit time, to a fine bin)*/
+/*   after transit   m <= o < 2m          (one duration after egress)       */
+/*   before transit  o >= max(2m, nb - m) (one duration before ingress)     */
+/* Transit number of a point: k = floor((ip nb + b - j) / nb), the cycle in */
+/* which its window starts; a transit counts when at least one in-transit   */
+/* point has its number.  Out-of-transit level: sum w y / sum w over points  */
+/* not in transit.  Candidate: at least two transits and S/N > 9.            */
+/* out: n_in, n_before, n_after, n_transits, candidate (as doubles), level.  */
+/* ------------------------------------------------------------------------- */
+static int64_t orc_floor_div(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) q -= 1;
+  return q;
+}
+
+static int orc_cmp_i64(const void* a, const void* b) {
+  int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+  return (x < y) ? -1 : (x > y) ? 1 : 0;
+}
+
+int orc_stats(const double* t, const double* y, const double* w, int64_t n, double t0, double f,
+              int32_t nb, int32_t m, int32_t j, double snr, double* out) {
+  if (!t || !y || !out || n < 1 || nb < 1 || m < 1 || m >= nb || j < 0 || j >= nb) return ORC_E_ARG;
+  int64_t n_in = 0, n_before = 0, n_after = 0, nk = 0;
+  int64_t* ks = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  double sw = 0.0, swy = 0.0;
+  for (int64_t q = 0; q < n; ++q) {
+    double wq = w ? w[q] : 1.0;
+    if (!(wq > 0.0)) continue;
+    double p = (t[q] - t0) * f;
+    double ip = floor(p);
+    int32_t b = (int32_t)floor((p - ip) * (double)nb);
+    if (b >= nb) b = nb - 1;
+    int32_t o = b - j;
+    if (o < 0) o += nb;
+    if (o < m) {
+      ++n_in;
+      ks[nk++] = orc_floor_div((int64_t)ip * nb + b - j, nb);
+    } else {
+      if (o < 2 * m) ++n_after;
+      else if (o >= nb - m) ++n_before;
+      sw += wq;
+      swy += wq * y[q];
+    }
+  }
+  qsort(ks, (size_t)nk, sizeof(int64_t), orc_cmp_i64);
+  int64_t n_tr = 0;
+  for (int64_t q = 0; q < nk; ++q)
+    if (q == 0 || ks[q] != ks[q - 1]) ++n_tr;
+  free(ks);
+  out[0] = (double)n_in;
+  out[1] = (double)n_before;
+  out[2] = (double)n_after;
+  out[3] = (double)n_tr;
+  out[4] = (n_tr >= 2 && snr > 9.0) ? 1.0 : 0.0;
+  out[5] = sw > 0.0 ? swy / sw : NAN;
+  return ORC_OK;
+}
+
 /* Threads OpenMP would use (for reporting the CPU baseline's core count). */
 int32_t orc_max_threads(void) {
 #ifdef _OPENMP

@@ -108,6 +108,8 @@ def lib():
         L.orc_bls_star_at.restype = ctypes.c_int
         L.orc_bls_star_at.argtypes = [vp, vp, vp, i64, d, ctypes.POINTER(Params), d, d, vp, i64,
                                       ctypes.POINTER(Spectrum), ctypes.POINTER(Bounds)]
+        L.orc_stats.restype = ctypes.c_int
+        L.orc_stats.argtypes = [vp, vp, vp, i64, d, d, i32, i32, i32, d, vp]
         L.orc_median.restype = d
         L.orc_median.argtypes = [vp, i64]
         L.orc_sturges.restype = i32
@@ -306,6 +308,24 @@ def batch(t, y, w, offsets, rho=None, pmin=None, pmax=None, p: Params | None = N
         raise ValueError("oracle batch failed")
     out["fofs"] = fofs
     return out
+
+
+STATS_FIELDS = ("n_in", "n_before", "n_after", "n_transits", "candidate", "oot_level")
+
+
+def stats(t, y, w, t0: float, f: float, nb: int, m: int, j: int, snr: float) -> dict:
+    """Points in, before and after transit, transit count, candidate flag and the
+    out-of-transit level at one best window (Sec. 2.2 item 5 and the detection
+    criteria)."""
+    t, y, w = _f64(t), _f64(y), _f64(w)
+    out = np.zeros(6)
+    st = lib().orc_stats(_ptr(t), _ptr(y), _ptr(w), len(t), t0, f, nb, m, j, snr, _ptr(out))
+    if st != 0:
+        raise ValueError("oracle stats status %d" % st)
+    r = dict(zip(STATS_FIELDS, out.tolist()))
+    for k in STATS_FIELDS[:5]:
+        r[k] = int(r[k])
+    return r
 
 
 def max_threads() -> int:

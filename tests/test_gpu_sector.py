@@ -1,0 +1,117 @@
+"""GPU parity at full sector-scale size, in the launch configuration the benchmark
+times: the benchmark's first batch (256 stars of the 1-26-sector mix at 200-s
+cadence, ``synth.config4(256, start=0)``) in one pass.
+
+* Three full-size stars (24-26 sectors, 274k-297k points, 118k-306k frequencies,
+  one with up to 6,372 fine bins, i.e. more than one LDS pass) against the oracle's
+  full-spectrum results stored in ``golden/sector_stars.json`` (written by
+  ``golden/make_sector_golden.py``, which calls only the oracle): best-SR and
+  best-S/N indices exact (near-ties of the oracle's own values excepted, 1e-12),
+  the S/N summary, and SR and best window at ~300 sampled frequencies per star
+  computed by the oracle one by one.
+* Every other star of the batch: SR at four sampled frequencies against the
+  oracle, and properties that hold at any size (SR finite and non-negative, the
+  reported best-SR index is the first maximum of the spectrum, the period is the
+  grid's at the best-S/N index)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2302_01293_amd import synth
+
+import parity_util as pu
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sector_stars.json")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def batch():
+    return synth.config4(256, start=0)
+
+
+def _check_index(label, i_gpu, top):
+    """i_gpu must be the oracle's argmax, or tie with it to 1e-12 (top: [[i, v], ...])."""
+    i0, v0 = top[0]
+    if i_gpu == i0:
+        return
+    vals = dict((int(i), v) for i, v in top)
+    assert i_gpu in vals, "%s: index %d is not among the oracle's largest values (argmax %d)" % (label, i_gpu, i0)
+    _say("%s: index %d vs %d at a near-tie (%.17g vs %.17g)" % (label, i_gpu, i0, vals[i_gpu], v0))
+    assert abs(vals[i_gpu] - v0) <= pu.NEAR_TIE_RTOL * abs(v0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sector_batch_full_size(oracle, batch, precision):
+    from paper_2302_01293_amd import _lib
+    gold = json.load(open(GOLD))
+    assert gold["batch"] == dict(n_stars=256, start=0)
+    b = batch
+    _say("case sector batch: %d stars, %d points, precision %d" % (b.n_stars, b.n_points, precision))
+    ds = pu.fetch(pu.run_gpu(b, _lib.default_params(precision=precision)))
+    sr_all, best_all, res = ds._sr_host, ds._best_host, ds._res_host
+    rel_tol = pu.SR_RTOL if precision == 0 else 2e-5
+    worst = 0.0
+    for g in gold["stars"]:
+        s = g["star"]
+        t, y, w = b.star(s)
+        sl = ds.star_slice(s)
+        sr, best = sr_all[sl], best_all[sl]
+        assert len(sr) == g["n_freq"]
+        R, O = res[s], g["result"]
+        label = "sector star %d (%d pts, %d freqs)" % (s, g["n_points"], g["n_freq"])
+        if precision == 0:
+            _check_index(label + " SR", int(R["i_sr"]), g["top_sr"])
+            _check_index(label + " S/N", int(R["i_snr"]), g["top_snr"])
+            assert abs(R["snr"] - O["snr"]) <= 1e-6 * abs(O["snr"])
+            assert abs(R["sigma"] - O["sigma"]) <= 1e-6 * O["sigma"]
+            assert abs(R["trend"] - O["trend"]) <= 1e-6 * abs(O["trend"])
+            for k in ("t0", "duration", "depth"):
+                assert abs(R[k] - O[k]) <= 1e-6 * abs(O[k]), (label, k, R[k], O[k])
+            assert R["period"] == O["period"]
+        else:
+            _say("%s packed: best-S/N index %d (oracle %d), S/N %.4f (oracle %.4f)"
+                 % (label, R["i_snr"], O["i_snr"], R["snr"], O["snr"]))
+            if g["injected"]:
+                assert abs(R["period"] / O["period"] - 1) < 1e-3
+        nf = g["n_freq"]
+        idx = np.unique(np.concatenate([np.linspace(0, nf - 1, 256).astype(np.int64),
+                                        [int(i) for i, _ in g["top_sr"][:16]],
+                                        [int(i) for i, _ in g["top_snr"][:16]]]))
+        o = oracle.bls_star_at(t, y, w, idx, float(b.rho[s]))
+        rel = np.abs(sr[idx] - o.sr) / np.maximum(o.sr, 1e-300)
+        worst = max(worst, float(rel.max()))
+        assert rel.max() <= rel_tol, (label, float(rel.max()))
+        if precision == 0:
+            mm = np.nonzero((best["m"][idx] != o.m) | (best["j"][idx] != o.j))[0]
+            for q in mm:
+                i = idx[q]
+                t0 = t[np.nonzero(w > 0)[0][0]]
+                pg = pu.window_power(t, y, w, t0, o.f[q], o.nb[q], best["m"][i], best["j"][i])
+                po = pu.window_power(t, y, w, t0, o.f[q], o.nb[q], o.m[q], o.j[q])
+                assert abs(pg - po) <= pu.NEAR_TIE_RTOL * abs(po), (label, int(i))
+        _say("%s: %d sampled frequencies, max rel SR err %.3e" % (label, len(idx), rel.max()))
+    # every star of the batch: sampled SR and size-free properties
+    rng = np.random.default_rng(5)
+    for s in range(b.n_stars):
+        sl = ds.star_slice(s)
+        sr = sr_all[sl]
+        assert np.all(np.isfinite(sr)) and np.all(sr >= 0)
+        assert int(res["i_sr"][s]) == int(np.argmax(sr))
+        assert res["sr"][s] == sr[int(res["i_snr"][s])]
+        f, _ = ds.plan.frequencies(s)
+        assert res["period"][s] == 1.0 / f[int(res["i_snr"][s])]
+        idx = np.unique(rng.integers(0, len(sr), 4))
+        t, y, w = b.star(s)
+        o = oracle.bls_star_at(t, y, w, idx, float(b.rho[s]))
+        rel = np.abs(sr[idx] - o.sr) / np.maximum(o.sr, 1e-300)
+        worst = max(worst, float(rel.max()))
+        assert rel.max() <= rel_tol, (s, float(rel.max()))
+    _say("sector batch precision %d: max rel SR err over every sample %.3e" % (precision, worst))

@@ -453,3 +453,82 @@ def test_sampled_frequencies_equal_the_full_search(oracle):
         assert np.array_equal(getattr(part, k), getattr(full, k)[idx]), k
     with pytest.raises(ValueError):
         oracle.bls_star_at(t, y, w, [len(full.sr)], float(b.rho[1]))
+
+
+# ---------------------------------------------------------------------------
+# Other statistics and the detection criteria (Sec. 2.2 item 5 and the
+# paragraph after the list): hand-built light curves with known counts
+# ---------------------------------------------------------------------------
+def _grid_curve(cycles=10):
+    # 128 points per unit period at exact binary times: with f = 1 and nb = 64 every
+    # fine bin holds two points (phases k/128), no rounding anywhere
+    t = np.arange(128 * cycles, dtype=np.float64) / 128.0
+    return t
+
+
+def test_stats_counts_on_a_regular_grid(oracle):
+    t = _grid_curve()
+    w = np.ones_like(t)
+    y = np.ones_like(t)
+    b = (np.arange(len(t)) % 128) // 2          # bin of each point, by construction
+    y[(b >= 20) & (b < 26)] -= 1e-3
+    s = oracle.stats(t, y, w, 0.0, 1.0, 64, 6, 20, 10.0)
+    # window bins 20..25: 6 bins x 2 points x 10 cycles; after: bins 26..31; before: 14..19
+    assert (s["n_in"], s["n_after"], s["n_before"], s["n_transits"]) == (120, 120, 120, 10)
+    assert s["candidate"] == 1 and s["oot_level"] == 1.0
+    # two cycles without data: two transits fewer
+    keep = (t < 2.0) | (t >= 4.0)
+    s = oracle.stats(t[keep], y[keep], w[keep], 0.0, 1.0, 64, 6, 20, 10.0)
+    assert (s["n_in"], s["n_transits"]) == (96, 8)
+    # zero-weight points are not data: cycle 5's transit vanishes
+    w5 = w.copy()
+    w5[(t >= 5.0) & (t < 6.0) & (b >= 20) & (b < 26)] = 0.0
+    s = oracle.stats(t, y, w5, 0.0, 1.0, 64, 6, 20, 10.0)
+    assert (s["n_in"], s["n_transits"]) == (108, 9)
+    # one in-transit point is enough for a transit to count
+    drop = (t >= 7.0) & (t < 8.0) & (b >= 20) & (b < 26)
+    drop[np.nonzero(drop)[0][-1]] = False
+    s = oracle.stats(t[~drop], y[~drop], w[~drop], 0.0, 1.0, 64, 6, 20, 10.0)
+    assert (s["n_in"], s["n_transits"]) == (109, 10)
+
+
+def test_stats_window_wrapping_past_the_last_bin(oracle):
+    # window bins 61, 62, 63, 0, 1, 2: the points in bins 0-2 of the first cycle
+    # belong to a transit whose mid-time falls before t0, so 11 transits
+    t = _grid_curve()
+    w = np.ones_like(t)
+    y = np.ones_like(t)
+    s = oracle.stats(t, y, w, 0.0, 1.0, 64, 6, 61, 12.0)
+    assert (s["n_in"], s["n_after"], s["n_before"], s["n_transits"]) == (120, 120, 120, 11)
+
+
+def test_stats_oot_level_and_criteria(oracle):
+    t = _grid_curve()
+    w = np.ones_like(t)
+    b = (np.arange(len(t)) % 128) // 2
+    intr = (b >= 20) & (b < 26)
+    y = np.where(intr, 0.5, 1.0)
+    y[(t < 1.0) & ~intr] = 2.0                     # out-of-transit points of cycle 0 at 2
+    s = oracle.stats(t, y, w, 0.0, 1.0, 64, 6, 20, 9.5)
+    assert abs(s["oot_level"] - (116 * 2.0 + 9 * 116 * 1.0) / (10 * 116)) <= 1e-15
+    assert s["candidate"] == 1
+    assert oracle.stats(t, y, w, 0.0, 1.0, 64, 6, 20, 9.0)["candidate"] == 0   # S/N > 9, strict
+    one = t < 1.0
+    assert oracle.stats(t[one], y[one], w[one], 0.0, 1.0, 64, 6, 20, 50.0)["candidate"] == 0  # one transit
+
+
+def test_stats_in_transit_set_is_the_best_window(oracle):
+    # the noiseless aligned box: in-transit points are exactly the injected ones and
+    # their weight fraction is the search's r of the best window
+    m_true, depth = 6, 2e-3
+    t, y, i, fi, nbi, j0, intr = _aligned_box(oracle, m_true, depth)
+    sp = oracle.bls_star(t, y, None, 1.0, pmin=0.5, pmax=13.7)
+    s = oracle.stats(t, y, None, float(t[0]), float(sp.f[i]), int(sp.nb[i]), int(sp.m[i]), int(sp.j[i]), 20.0)
+    assert s["n_in"] == int(intr.sum())
+    assert abs(s["n_in"] / len(t) - sp.r[i]) <= 1e-12
+    assert s["oot_level"] == 1.0
+    # one transit per period over the 27.4-d span (the data gap holds none of them here)
+    P = 1.0 / fi
+    mids = t[0] + ((j0 + m_true / 2) / nbi + np.arange(-1, 30)) * P
+    covered = [np.any(np.abs(t - c) <= 0.5 * m_true / (nbi * fi)) for c in mids]
+    assert s["n_transits"] == int(np.sum(covered))
