@@ -54,7 +54,9 @@ enum {
   BLS_E_NOMEM = -4,       /* host allocation failed */
   BLS_E_HIP = -5,         /* a HIP call failed (launch or copy) */
   BLS_E_STATE = -6,       /* workspace missing, too small or not uploaded */
-  BLS_E_UNSUPPORTED = -7  /* a star exceeds a compiled limit (see bls_limits) */
+  BLS_E_UNSUPPORTED = -7, /* a star exceeds a compiled limit (see bls_limits) */
+  BLS_E_SCRATCH = -8      /* the plan's workspace exceeds the static scratch of
+                             bls_run_noalloc (MI355BLS_NOALLOC_SCRATCH_BYTES) */
 };
 
 /* Search parameters.  bls_default_params() fills the paper's values (Sec. 2.1,
@@ -195,6 +197,24 @@ const char* bls_status_string(bls_status s);
 /* HIP error code (hipError_t value) of the last HIP call that failed inside the
  * library on the calling thread, behind a BLS_E_HIP return; 0 if none. */
 int32_t bls_last_hip_error(void);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the whole device path of a
+ * plan -- bls_plan_upload, bls_prepare, bls_search_batch and bls_snr with the same
+ * arguments and results -- on a workspace held in a static device array of
+ * MI355BLS_NOALLOC_SCRATCH_BYTES bytes (one per GPU, kept until the process ends)
+ * instead of a caller allocation.  The caller still owns the inputs d_t, d_y, d_w
+ * (w nullable) and the outputs d_sr, d_best (nullable), d_snr (nullable) and
+ * d_result; d_windows / n_windows as for bls_search_batch.  Returns BLS_E_SCRATCH,
+ * enqueueing nothing, when the plan's workspace (bls_plan_query) is larger.  Calls no
+ * allocating routine.  Every call on a GPU uses that GPU's one array: calls that
+ * overlap on one GPU (other streams, other threads) race and must be serialised by
+ * the caller; a plan used here is uploaded to that array, so a later bls_prepare /
+ * bls_search_batch / bls_snr on it needs a bls_plan_upload to its own workspace. */
+#define MI355BLS_NOALLOC_SCRATCH_BYTES (64LL << 20)
+bls_status bls_run_noalloc(bls_plan* plan, const double* d_t, const double* d_y, const double* d_w,
+                           const int64_t* d_windows, int64_t n_windows, double* d_sr, bls_best* d_best,
+                           double* d_snr, bls_result* d_result, bls_stream_t stream);
 
 /* Compiled limits: out[0] = maximum fine bins per frequency, out[1] = maximum
  * duration-ladder length, out[2] = maximum points per star. */

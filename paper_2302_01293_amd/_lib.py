@@ -16,11 +16,12 @@ LIB_PATH = os.path.join(HERE, "libmi355bls.so")
 
 BLS_OK = 0
 STATUS_NAMES = {0: "BLS_OK", -1: "BLS_E_ARG", -2: "BLS_E_INPUT", -3: "BLS_E_EMPTY_GRID",
-                -4: "BLS_E_NOMEM", -5: "BLS_E_HIP", -6: "BLS_E_STATE", -7: "BLS_E_UNSUPPORTED"}
+                -4: "BLS_E_NOMEM", -5: "BLS_E_HIP", -6: "BLS_E_STATE", -7: "BLS_E_UNSUPPORTED",
+                -8: "BLS_E_SCRATCH"}
 
 EXPORTS = ("bls_default_params", "bls_plan_create", "bls_plan_query", "bls_plan_star_info",
            "bls_plan_frequencies", "bls_plan_durations", "bls_plan_upload", "bls_prepare", "bls_search_batch",
-           "bls_snr", "bls_plan_destroy", "bls_status_string", "bls_limits", "bls_last_hip_error",
+           "bls_snr", "bls_run_noalloc", "bls_plan_destroy", "bls_status_string", "bls_limits", "bls_last_hip_error",
            # learned period proposal (include/mi355pp.h)
            "pp_act_bytes", "pp_resample", "pp_forward", "pp_backward", "pp_adam", "pp_propose",
            "pp_tile_capacity", "pp_snr_windows")
@@ -106,6 +107,8 @@ def lib():
         L.bls_search_batch.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.bls_snr.restype = i32
         L.bls_snr.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.bls_run_noalloc.restype = i32
+        L.bls_run_noalloc.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp]
         L.bls_plan_destroy.restype = None
         L.bls_plan_destroy.argtypes = [vp]
         L.bls_status_string.restype = ctypes.c_char_p
@@ -250,6 +253,19 @@ class Plan:
         st = lib().bls_snr(self.h, d_ws, d_sr, d_best or None, d_snr or None, d_result, stream or None)
         if st != BLS_OK:
             raise BlsError("bls_snr", st)
+
+    def run_noalloc(self, d_t: int, d_y: int, d_w: int | None, d_sr: int, d_best: int | None,
+                    d_snr: int | None, d_result: int, d_windows: int | None = None, n_windows: int = 0,
+                    stream: int = 0):
+        """upload -> prepare -> search -> S/N on the library's static device scratch
+        (``bls_run_noalloc``: no workspace argument, nothing allocated)."""
+        st = lib().bls_run_noalloc(self.h, d_t, d_y, d_w or None, d_windows or None, n_windows, d_sr,
+                                   d_best or None, d_snr or None, d_result, stream or None)
+        if st != BLS_OK:
+            raise BlsError("bls_run_noalloc", st)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def check(name: str, st: int):

@@ -378,6 +378,7 @@ extern "C" const char* bls_status_string(bls_status s) {
     case BLS_E_HIP: return "HIP call failed";
     case BLS_E_STATE: return "workspace missing, too small or not uploaded";
     case BLS_E_UNSUPPORTED: return "star exceeds a compiled limit";
+    case BLS_E_SCRATCH: return "workspace larger than the static scratch of bls_run_noalloc";
     default: return "unknown status";
   }
 }

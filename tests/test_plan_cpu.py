@@ -173,3 +173,16 @@ def test_concat_keeps_stars_and_common_truth():
         assert all(np.array_equal(u, v) for u, v in zip(c.star(5 + s), b.star(s)))
     assert set(c.truth) == set(a.truth) & set(b.truth)
     assert np.array_equal(c.truth["period"][5:], b.truth["period"], equal_nan=True)
+
+
+def test_noalloc_rejects_plan_larger_than_scratch():
+    """bls_run_noalloc refuses a plan whose workspace exceeds its static scratch
+    before it touches any pointer or the device (host check, no GPU needed)."""
+    from paper_2302_01293_amd import _lib, synth
+    b = synth.config1(300, start=0)          # 300 x 11,405 points x 24 B > 64 MiB
+    pl = _lib.Plan(b.t, b.y, b.w, b.offsets, b.rho, b.pmin, b.pmax)
+    assert pl.workspace_bytes > _lib.NOALLOC_SCRATCH_BYTES
+    with pytest.raises(_lib.BlsError) as e:
+        pl.run_noalloc(1, 1, None, 1, None, None, 1)
+    assert e.value.code == -8
+    assert _lib.lib().bls_status_string(-8).startswith(b"workspace larger")
