@@ -115,6 +115,18 @@ typedef struct bls_result {
   int32_t nbins;       /* Sturges bin count used for the trend */
 } bls_result;
 
+/* Other statistics of a star's detection (Sec. 2.2 item 5) and its detection
+ * criteria (the paragraph after the list), written by bls_stats(). */
+typedef struct bls_star_stats {
+  int64_t n_in;        /* points (w > 0) in transit: in the best window's m fine bins */
+  int64_t n_before;    /* points within one duration before ingress */
+  int64_t n_after;     /* points within one duration after egress */
+  int64_t n_transits;  /* transits with data within half a duration of mid-transit */
+  double oot_level;    /* sum w y / sum w over the points out of transit (NaN if none) */
+  int32_t candidate;   /* 1: n_transits >= 2 and S/N > the threshold (9 in the note) */
+  int32_t status;      /* 0 ok; 1 no valid window at the detection frequency (counts 0) */
+} bls_star_stats;
+
 typedef struct bls_plan bls_plan;
 
 /* Fill *p with the paper's parameters. */
@@ -187,6 +199,23 @@ bls_status bls_search_batch(bls_plan* plan, void* d_workspace, const int64_t* d_
  * S/N per frequency.  d_result (device [n_stars]) gets the summary. */
 bls_status bls_snr(bls_plan* plan, void* d_workspace, const double* d_sr, const bls_best* d_best,
                    double* d_snr, bls_result* d_result, bls_stream_t stream);
+
+/* Other statistics of each star's detection (Sec. 2.2 item 5) and the detection
+ * criteria of the paragraph after that list, at the best window (m fine bins from
+ * bin j, from d_best) of the detection frequency i_snr (from d_result), using the
+ * search's own phase fold of f_i with nb_i fine bins.  A point (w > 0) is in transit
+ * when its bin lies in the window (within half a duration of mid-transit, to one fine
+ * bin), after transit in the m bins that follow, before transit in the m bins that
+ * precede (never both); a transit counts when at least one in-transit point falls
+ * in its cycle.  candidate = (n_transits >= 2 && S/N > snr_min); the note's
+ * threshold is 9, and its third criterion (S/N_pink, from the trapezoid fit of items
+ * 2-4) is not part of this flag.  Device inputs: the packed t, y, w (w nullable:
+ * unit weights) given to bls_prepare, d_best [n_freq_total] and d_result [n_stars]
+ * of the same plan; output d_stats [n_stars].  The workspace must hold the plan
+ * (bls_plan_upload).  Enqueued on stream; allocates nothing. */
+bls_status bls_stats(bls_plan* plan, void* d_workspace, const double* d_t, const double* d_y, const double* d_w,
+                     const bls_best* d_best, const bls_result* d_result, double snr_min,
+                     bls_star_stats* d_stats, bls_stream_t stream);
 
 /* Release a plan (host memory only). */
 void bls_plan_destroy(bls_plan* plan);

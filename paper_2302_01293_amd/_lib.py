@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "BLS_OK", -1: "BLS_E_ARG", -2: "BLS_E_INPUT", -3: "BLS_E_EMPT
 
 EXPORTS = ("bls_default_params", "bls_plan_create", "bls_plan_query", "bls_plan_star_info",
            "bls_plan_frequencies", "bls_plan_durations", "bls_plan_upload", "bls_prepare", "bls_search_batch",
-           "bls_snr", "bls_run_noalloc", "bls_plan_destroy", "bls_status_string", "bls_limits", "bls_last_hip_error",
+           "bls_snr", "bls_stats", "bls_run_noalloc", "bls_plan_destroy", "bls_status_string", "bls_limits", "bls_last_hip_error",
            # learned period proposal (include/mi355pp.h)
            "pp_act_bytes", "pp_resample", "pp_forward", "pp_backward", "pp_adam", "pp_propose",
            "pp_tile_capacity", "pp_snr_windows")
@@ -52,7 +52,10 @@ RESULT_DTYPE = np.dtype([("i_snr", np.int64), ("i_sr", np.int64), ("period", np.
                          ("t0", np.float64), ("duration", np.float64), ("depth", np.float64),
                          ("sr", np.float64), ("snr", np.float64), ("trend", np.float64),
                          ("sigma", np.float64), ("status", np.int32), ("nbins", np.int32)])
-assert BEST_DTYPE.itemsize == 24 and RESULT_DTYPE.itemsize == 88
+STATS_DTYPE = np.dtype([("n_in", np.int64), ("n_before", np.int64), ("n_after", np.int64),
+                        ("n_transits", np.int64), ("oot_level", np.float64), ("candidate", np.int32),
+                        ("status", np.int32)])
+assert BEST_DTYPE.itemsize == 24 and RESULT_DTYPE.itemsize == 88 and STATS_DTYPE.itemsize == 48
 
 _lib = None
 
@@ -107,6 +110,8 @@ def lib():
         L.bls_search_batch.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.bls_snr.restype = i32
         L.bls_snr.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.bls_stats.restype = i32
+        L.bls_stats.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp]
         L.bls_run_noalloc.restype = i32
         L.bls_run_noalloc.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp]
         L.bls_plan_destroy.restype = None
@@ -253,6 +258,13 @@ class Plan:
         st = lib().bls_snr(self.h, d_ws, d_sr, d_best or None, d_snr or None, d_result, stream or None)
         if st != BLS_OK:
             raise BlsError("bls_snr", st)
+
+    def stats(self, d_ws: int, d_t: int, d_y: int, d_w: int | None, d_best: int, d_result: int,
+              d_stats: int, snr_min: float = 9.0, stream: int = 0):
+        st = lib().bls_stats(self.h, d_ws, d_t, d_y, d_w or None, d_best, d_result, float(snr_min), d_stats,
+                             stream or None)
+        if st != BLS_OK:
+            raise BlsError("bls_stats", st)
 
     def run_noalloc(self, d_t: int, d_y: int, d_w: int | None, d_sr: int, d_best: int | None,
                     d_snr: int | None, d_result: int, d_windows: int | None = None, n_windows: int = 0,

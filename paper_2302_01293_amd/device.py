@@ -46,6 +46,7 @@ class DeviceSearch:
         self.best = torch.empty(nf * BEST_DTYPE.itemsize, dtype=torch.uint8, device=dev) if want_best else None
         self.snr = torch.empty(nf, dtype=torch.float64, device=dev) if want_snr else None
         self.result = torch.empty(self.plan.n_stars * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        self.stats = None
         self.plan.upload(self.ws_ptr, self.plan.workspace_bytes, _stream_handle())
 
     @classmethod
@@ -73,6 +74,21 @@ class DeviceSearch:
         h = _stream_handle(stream)
         self.plan.snr(self.ws_ptr, self.sr.data_ptr(), None if self.best is None else self.best.data_ptr(),
                       None if self.snr is None else self.snr.data_ptr(), self.result.data_ptr(), stream=h)
+
+    def run_stats(self, snr_min: float = 9.0, stream=None):
+        """Per-star statistics and detection criteria at each star's detection
+        (``bls_stats``; needs the best windows, i.e. ``want_best``)."""
+        if self.best is None:
+            raise RuntimeError("bls_stats needs the per-frequency best windows (want_best=True)")
+        if self.stats is None:
+            self.stats = torch.empty(self.plan.n_stars * _lib.STATS_DTYPE.itemsize, dtype=torch.uint8,
+                                     device=self.device)
+        self.plan.stats(self.ws_ptr, self.t.data_ptr(), self.y.data_ptr(),
+                        None if self.w is None else self.w.data_ptr(), self.best.data_ptr(),
+                        self.result.data_ptr(), self.stats.data_ptr(), snr_min, stream=_stream_handle(stream))
+
+    def stats_host(self) -> np.ndarray:
+        return self.stats.cpu().numpy().view(_lib.STATS_DTYPE)
 
     def run(self, stream=None, windows=None):
         self.run_prepare(stream)
