@@ -98,6 +98,27 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def measure_ceilings(copy_mib: int = 2048) -> dict:
+    """Unit rates measured on this GPU by libmi355ceil.so (csrc/ceilings.hip): the
+    FP64 multiply / fract / convert issue costs, the 64-bit LDS atomic cost per wave
+    instruction, and an HBM copy rate, next to which the vendor peaks are quoted."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2302_01293_amd", "libmi355ceil.so")
+    L = ctypes.CDLL(path)
+    L.mi355_ceilings.restype = ctypes.c_int
+    L.mi355_ceilings.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    out = np.zeros(8)
+    st = L.mi355_ceilings(out.ctypes.data, int(copy_mib) << 20)
+    if st != 0:
+        raise RuntimeError("mi355_ceilings failed (hipError %d)" % st)
+    clk = out[7] * 1e9
+    return {"dmul_simd_cycles": out[0], "fract_simd_cycles": out[1], "cvt_plus_xor_simd_cycles": out[2],
+            "iadd_simd_cycles": out[3], "lds_add_u64_cu_cycles_64_lanes": out[4],
+            "lds_add_u64_cu_cycles_1_lane": out[5], "hbm_copy_GBps": out[6], "clock_GHz": out[7],
+            "fp64_ops_per_s": 1024 * 64 / out[0] * clk,
+            "lds_atomic_instr_per_s": 256 / out[4] * clk}
+
+
 def make_workload(name: str, n_stars: int, batch_stars: int, steps: int):
     """List of batches (one per step for the sector-scale mix; one shared batch
     otherwise) and a description."""
@@ -218,6 +239,7 @@ def main():
                     help="cfg4: steps' batches on which the learned path is compared with the plain one")
     ap.add_argument("--learned-points", default="0.9:8,0.95:12",
                     help="confidence:top-k operating points of the learned path")
+    ap.add_argument("--no-ceilings", action="store_true", help="skip the unit-rate microbenchmarks")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size kernel "
                          "for scaling the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -373,6 +395,14 @@ def main():
                      "kernel": "k_search (fold + boundary accumulation + scan; all launches of "
                                "bls_search_batch)"},
     }
+    if not args.no_ceilings:
+        c = measure_ceilings()
+        out["ceilings"] = c
+        out["roofline"]["measured_peak"] = c["fp64_ops_per_s"] / 1e12
+        out["roofline"]["frac_of_measured"] = achieved / (c["fp64_ops_per_s"] / 1e12)
+        log("ceilings: DMUL %.2f FRACT %.2f SIMD-cycles per wave instruction; 64-bit LDS atomic %.2f CU-cycles; "
+            "copy %.0f GB/s" % (c["dmul_simd_cycles"], c["fract_simd_cycles"], c["lds_add_u64_cu_cycles_64_lanes"],
+                                c["hbm_copy_GBps"]))
     if not args.no_learned:
         out["learned"] = learned_vs_plain(args, steps, results, dev_ms, params)
     if not args.no_cpu_baseline:

@@ -33,6 +33,26 @@ def command(out: str) -> list[str]:
             "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-o", out] + srcs
 
 
+CEIL_LIB = os.path.join(HERE, "libmi355ceil.so")
+
+
+def build_ceilings(verbose: bool = False) -> str:
+    """The unit-rate microbenchmarks (``csrc/ceilings.hip``) as their own library."""
+    tmp = CEIL_LIB + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), "-O3", "--offload-arch=" + ARCH, "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-o", tmp,
+           os.path.join(CSRC, "ceilings.hip")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    noise = "is not a recognized feature for this target"
+    err = "\n".join(l for l in (res.stderr or "").splitlines() if noise not in l)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + err)
+    os.replace(tmp, CEIL_LIB)
+    return CEIL_LIB
+
+
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = command(tmp)
@@ -51,3 +71,4 @@ def build(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_ceilings(verbose=True))
