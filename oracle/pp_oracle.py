@@ -24,7 +24,12 @@ Definitions followed here, in order:
   probability mass inside the windows; below the threshold the full grid is used;
 * windowed S/N: trend and sigma from a coarse spectrum (Sturges bins, medians,
   linear interpolation, 1.4826 MAD; Sec. 2.2 item 1 and its footnote) applied to
-  the SR of the window frequencies.
+  the SR of the window frequencies;
+* coarse-peak windows (guided proposal): the n largest values of the coarse
+  spectrum's S/N, each more than h coarse steps from every larger one chosen
+  before it (ties to the lower index), each widened by h coarse steps on both sides
+  and mapped to the fine grid (both grids are uniform in u = f^(1/3) from the same
+  u_min), added to the network's windows; overlapping or touching ranges merged.
 """
 from __future__ import annotations
 
@@ -358,3 +363,78 @@ def window_snr(f_coarse, sr_coarse, f_fine, sr_fine, ranges, sturges):
             if v > best_v:
                 best_i, best_v = i, v
     return best_i, best_v, sigma
+
+
+# ---------------------------------------------------------------------------
+# guided proposal: coarse-peak windows
+# ---------------------------------------------------------------------------
+def coarse_peaks(snr_coarse, n_peaks: int, halfwidth: int):
+    """Indices of the n_peaks largest coarse S/N values, largest first; each pick
+    blocks the picks within halfwidth coarse steps of it; ties to the lower index."""
+    v = np.asarray(snr_coarse, np.float64)
+    picks = []
+    for _ in range(n_peaks):
+        best = -1
+        for i in range(len(v)):
+            if any(abs(i - q) <= halfwidth for q in picks):
+                continue
+            if best < 0 or v[i] > v[best]:
+                best = i
+        if best < 0:
+            break
+        picks.append(best)
+    return picks
+
+
+def coarse_windows(picks, umin_c, A_c, nf_c, umin, A, nf, halfwidth: int):
+    """Fine index ranges [i0, i1) covering coarse indices pick +- halfwidth (clipped
+    to the coarse grid): i0 = ceil((u_c(lo) - u_min) / A), i1 - 1 = floor((u_c(hi) -
+    u_min) / A), clipped to [0, nf)."""
+    out = []
+    for ic in picks:
+        lo, hi = max(0, ic - halfwidth), min(nf_c - 1, ic + halfwidth)
+        a = math.ceil(((umin_c + lo * A_c) - umin) / A)
+        e = math.floor(((umin_c + hi * A_c) - umin) / A)
+        i0, i1 = max(0, a), min(nf - 1, e)
+        if i1 >= i0:
+            out.append((i0, i1 + 1))
+    return out
+
+
+def merge_ranges(ranges):
+    """Union of index ranges as sorted disjoint ranges (touching ranges join)."""
+    out = []
+    for a, b in sorted(ranges):
+        if out and a <= out[-1][1]:
+            out[-1] = (out[-1][0], max(out[-1][1], b))
+        else:
+            out.append((a, b))
+    return out
+
+
+def propose_guided(logits, pmin, pmax, umin, A, nf, snr_coarse, umin_c, A_c, n_peaks, halfwidth,
+                   topk=TOPK, conf=CONF):
+    """The proposal of ``propose`` (topk may be 0) with the coarse-peak windows added
+    to a confident star's windows (a star that falls back searches its full grid)."""
+    if topk > 0:
+        ranges, c, fb = propose(logits, pmin, pmax, umin, A, nf, topk, conf)
+    else:
+        pr = softmax(np.asarray(logits, np.float64))
+        c = float(pr[NPB])
+        fb = c < conf
+        ranges = [(0, nf)]
+        if not fb:
+            ranges = []
+            if pmax > PB_HI:
+                lo, hi = max(PB_HI, pmin), pmax
+                if hi > lo:
+                    i0 = max(0, int(math.ceil(((1.0 / hi) ** (1.0 / 3.0) - umin) / A)))
+                    i1 = min(nf - 1, int(math.floor(((1.0 / lo) ** (1.0 / 3.0) - umin) / A)))
+                    if i1 >= i0:
+                        ranges.append((i0, i1 + 1))
+    if fb:
+        return [(0, nf)], c, True
+    picks = coarse_peaks(snr_coarse, n_peaks, halfwidth)
+    ranges = merge_ranges(list(ranges) + coarse_windows(picks, umin_c, A_c, len(snr_coarse), umin, A, nf,
+                                                         halfwidth))
+    return ranges, c, False

@@ -169,3 +169,70 @@ def test_window_snr_equals_plain_snr_on_full_grid(oracle):
     i, v, sigma = P.window_snr(f, sp.sr, f, sp.sr, [(0, len(f))], oracle.sturges(len(f)))
     assert i == res.i_snr and abs(v - res.snr_max) <= 1e-12 * abs(res.snr_max)
     assert abs(sigma - res.sigma) <= 1e-14 * sigma
+
+
+def test_coarse_peaks_hand_built():
+    """Largest first, each pick blocks +-h, ties to the lower index."""
+    v = np.zeros(40)
+    v[10], v[12], v[30], v[5] = 5.0, 4.0, 3.0, 5.0   # 5 and 10 tie; 12 is within h=2 of 10
+    assert P.coarse_peaks(v, 3, 2) == [5, 10, 30]
+    assert P.coarse_peaks(v, 1, 2) == [5]
+    assert P.coarse_peaks(v, 4, 2) == [5, 10, 30, 0]    # then the first free zero (0..2 free of 5+-2)
+    assert P.coarse_peaks(np.ones(3), 5, 1) == [0, 2]   # the grid runs out
+
+
+def test_coarse_windows_map_u_ranges_to_the_fine_grid():
+    """A coarse grid with 16 times the fine step from the same u_min: coarse index i
+    is fine index 16 i, so +-h coarse steps are fine [16 (i - h), 16 (i + h)]."""
+    umin, A = 0.25, 1e-4
+    nf = 5000
+    w = P.coarse_windows([100, 3, 311, 313], umin, 16 * A, 314, umin, A, nf, 2)
+    assert w[0] == (16 * 98, 16 * 102 + 1)
+    assert w[1] == (16 * 1, 16 * 5 + 1)
+    assert w[2] == (16 * 309, nf)                          # clipped to the fine grid (16 * 313 > nf - 1)
+    assert w[3] == (16 * 311, nf)                          # and to the coarse grid (313 + 2 > 313)
+    assert P.coarse_windows([0], umin, 16 * A, 313, umin, A, nf, 3) == [(0, 16 * 3 + 1)]
+
+
+def test_merge_ranges_is_the_union():
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        rs = []
+        for _ in range(rng.integers(1, 9)):
+            a = int(rng.integers(0, 200))
+            rs.append((a, a + int(rng.integers(1, 30))))
+        m = P.merge_ranges(rs)
+        cov = set()
+        for a, b in rs:
+            cov.update(range(a, b))
+        got = set()
+        for a, b in m:
+            got.update(range(a, b))
+        assert got == cov
+        assert all(m[i][1] < m[i + 1][0] for i in range(len(m) - 1))   # disjoint, not touching
+
+
+def test_guided_proposal_adds_the_coarse_peak_and_keeps_fallback():
+    """A confident network window elsewhere plus a coarse peak: both ranges are
+    searched; a star that falls back still searches its full grid only."""
+    umin, A = (1.0 / 13.7) ** (1 / 3), 2e-5
+    nf = int(((1 / 0.35) ** (1 / 3) - umin) / A) + 1
+    z = np.full(P.NPB + 1, -5.0)
+    z[200] = 10.0
+    snr_c = np.zeros(nf // 16)
+    snr_c[1000] = 12.0
+    r, c, fb = P.propose_guided(z, 0.35, 13.7, umin, A, nf, snr_c, umin, 16 * A, 1, 3)
+    assert not fb
+    base, _, _ = P.propose(z, 0.35, 13.7, umin, A, nf)
+    cw = P.coarse_windows([1000], umin, 16 * A, len(snr_c), umin, A, nf, 3)
+    assert r == P.merge_ranges(base + cw)
+    assert any(a <= 16 * 1000 < b for a, b in r)
+    r2, c2, fb2 = P.propose_guided(np.zeros(P.NPB + 1), 0.35, 13.7, umin, A, nf, snr_c, umin, 16 * A, 1, 3)
+    assert fb2 and r2 == [(0, nf)]
+    # topk = 0: the null probability alone is the confidence; only coarse windows
+    z0 = np.full(P.NPB + 1, -20.0)
+    z0[P.NPB] = 10.0
+    r3, c3, fb3 = P.propose_guided(z0, 0.35, 13.7, umin, A, nf, snr_c, umin, 16 * A, 2, 3, topk=0, conf=0.5)
+    assert not fb3 and c3 > 0.99
+    assert r3 == P.merge_ranges(P.coarse_windows(P.coarse_peaks(snr_c, 2, 3), umin, 16 * A, len(snr_c),
+                                                 umin, A, nf, 3))
