@@ -237,8 +237,10 @@ def main():
                     help="skip the learned-proposal comparison (trained weights vs the plain path)")
     ap.add_argument("--learned-batches", type=int, default=8,
                     help="cfg4: steps' batches on which the learned path is compared with the plain one")
-    ap.add_argument("--learned-points", default="0.9:8,0.95:12",
-                    help="confidence:top-k operating points of the learned path")
+    ap.add_argument("--learned-points", default="0.5:8:4,0.9:8:0,0:0:4,0:0:2,0:8:2",
+                    help="operating points of the learned path, conf:topk:coarse_peaks (coarse_peaks > 0: "
+                         "windows guided by that many peaks of the coarse S/N spectrum, no blanket window "
+                         "beyond 100 d; topk 0: no network windows); the first is the headline")
     ap.add_argument("--no-ceilings", action="store_true", help="skip the unit-rate microbenchmarks")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size kernel "
@@ -430,15 +432,17 @@ def learned_vs_plain(args, steps, plain_results, plain_ms, params):
     out = dict(weights="paper_2302_01293_amd/pp_weights.npy", batches=nb,
                stars=int(sum(steps[k].batch.n_stars for k in range(nb))), points=[])
     for spec in args.learned_points.split(","):
-        conf, topk = spec.split(":")
-        conf, topk = float(conf), int(topk)
+        parts = spec.split(":")
+        conf, topk = float(parts[0]), int(parts[1])
+        peaks = int(parts[2]) if len(parts) > 2 else 0
+        kw = dict(topk=topk, conf=conf, coarse_peaks=peaks, search_long=peaks == 0)
         t_l = t_p = 0.0
         agg = dict(plain_detections=0, recovered=0, exact_index=0)
         fb = searched = nf_all = 0.0
         conf_stats = dict(confident_detections=0, confident_recovered=0)
         for k in range(nb):
             b = steps[k].batch
-            ls = learned.LearnedSearch(b, net, params=params, topk=topk, conf=conf)
+            ls = learned.LearnedSearch(b, net, params=params, **kw)
             ls.run()
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -462,14 +466,22 @@ def learned_vs_plain(args, steps, plain_results, plain_ms, params):
             nf_all += ls.fine.plan.n_freq
             del ls
         n_stars = out["stars"]
-        pt = dict(conf=conf, topk=topk, plain_ms=t_p, learned_ms=t_l, speedup=t_p / t_l,
+        kind = ("network windows" if peaks == 0 else
+                "coarse-peak windows only (no network)" if topk == 0 else "network + coarse-peak windows")
+        pt = dict(conf=conf, topk=topk, coarse_peaks=peaks, kind=kind, plain_ms=t_p, learned_ms=t_l,
+                  speedup=t_p / t_l,
                   fallback_fraction=fb / n_stars, recovery=agg["recovered"] / max(agg["plain_detections"], 1),
                   **agg, **conf_stats)
         pt["searched_fraction"] = searched / nf_all
-        log("learned conf %.2f top-%d: recovery %d/%d (confident stars %d/%d), speed-up %.2fx, fallback %.3f"
-            % (conf, topk, agg["recovered"], agg["plain_detections"], conf_stats["confident_recovered"],
-               conf_stats["confident_detections"], pt["speedup"], pt["fallback_fraction"]))
+        log("learned conf %.2f top-%d coarse peaks %d: recovery %d/%d (confident stars %d/%d), speed-up %.2fx, "
+            "fallback %.3f" % (conf, topk, peaks, agg["recovered"], agg["plain_detections"],
+                               conf_stats["confident_recovered"], conf_stats["confident_detections"], pt["speedup"],
+                               pt["fallback_fraction"]))
         out["points"].append(pt)
+    h = out["points"][0]
+    out["headline"] = dict(kind=h["kind"], conf=h["conf"], topk=h["topk"], coarse_peaks=h["coarse_peaks"],
+                           recovery=h["recovery"], speedup=h["speedup"],
+                           stars_per_hour=out["stars"] / (h["learned_ms"] * 1e-3) * 3600.0)
     return out
 
 

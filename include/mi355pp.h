@@ -90,6 +90,23 @@ bls_status pp_propose(const bls_plan* plan, void* d_workspace, const float* d_lo
                       int64_t* d_windows, uint8_t* d_fallback, float* d_conf, int64_t* d_tiles,
                       bls_stream_t stream);
 
+/* pp_propose guided by a coarse search: for a star that does not fall back, the
+ * windows also cover the n_peaks largest values of d_coarse_snr (the S/N spectrum of
+ * plan `coarse`, from bls_snr: the same stars on the same u = f^(1/3) grid origin
+ * with fewer samples per peak), each chosen more than halfwidth coarse steps from
+ * every larger one (ties to the lower index) and widened by halfwidth coarse steps
+ * on both sides: fine indices from ceil((u_c(i - h) - u_min) / A) to
+ * floor((u_c(i + h) - u_min) / A).  All windows of a star are merged into sorted
+ * disjoint ranges.  search_long = 0 drops pp_propose's [100 d, Pmax] window (periods
+ * the network cannot see): the coarse peaks cover every period of the grid.  topk
+ * may be 0 (then c = P(null) and only the coarse peaks, with the long-period window
+ * if search_long, are searched).  topk + 1 + n_peaks <= PP_MAX_WINDOWS.
+ * Outputs as pp_propose.  Both plans must be uploaded to their workspaces. */
+bls_status pp_propose_guided(const bls_plan* plan, void* d_workspace, const float* d_logits, int32_t topk,
+                             float conf, int32_t search_long, const bls_plan* coarse, void* coarse_workspace, const double* d_coarse_snr,
+                             int32_t n_peaks, int32_t halfwidth, int64_t* d_windows, uint8_t* d_fallback,
+                             float* d_conf, int64_t* d_tiles, bls_stream_t stream);
+
 /* Rows of the tiled work list of pp_propose for a plan. */
 bls_status pp_tile_capacity(const bls_plan* plan, int64_t* n);
 

@@ -298,8 +298,9 @@ def adam(theta, m, v, g, step, lr, b1=0.9, b2=0.999, eps=1e-8):
 # ---------------------------------------------------------------------------
 # proposal
 # ---------------------------------------------------------------------------
-def propose(logits, pmin, pmax, umin, A, nf, topk=TOPK, conf=CONF):
-    """Frequency-index ranges [i0, i1) to search for one star, confidence, fallback."""
+def propose(logits, pmin, pmax, umin, A, nf, topk=TOPK, conf=CONF, pb_hi_window=True):
+    """Frequency-index ranges [i0, i1) to search for one star, confidence, fallback
+    (``pb_hi_window``: include the window over periods beyond 100 d)."""
     pr = softmax(np.asarray(logits, np.float64))
     pb = pr[:NPB]
     order = sorted(range(NPB), key=lambda k: (-pb[k], k))[:topk]
@@ -321,7 +322,7 @@ def propose(logits, pmin, pmax, umin, A, nf, topk=TOPK, conf=CONF):
             k = k1 + 1
         else:
             k += 1
-    if pmax > PB_HI:
+    if pb_hi_window and pmax > PB_HI:
         ivs.append((PB_HI, pmax))
     out = []
     for lo, hi in ivs:
@@ -413,11 +414,13 @@ def merge_ranges(ranges):
 
 
 def propose_guided(logits, pmin, pmax, umin, A, nf, snr_coarse, umin_c, A_c, n_peaks, halfwidth,
-                   topk=TOPK, conf=CONF):
+                   topk=TOPK, conf=CONF, search_long=True):
     """The proposal of ``propose`` (topk may be 0) with the coarse-peak windows added
-    to a confident star's windows (a star that falls back searches its full grid)."""
+    to a confident star's windows (a star that falls back searches its full grid);
+    ``search_long`` False drops the window over periods beyond 100 d."""
     if topk > 0:
-        ranges, c, fb = propose(logits, pmin, pmax, umin, A, nf, topk, conf)
+        ranges, c, fb = propose(logits, pmin, pmax, umin, A, nf, topk, conf,
+                                pb_hi_window=search_long)
     else:
         pr = softmax(np.asarray(logits, np.float64))
         c = float(pr[NPB])
@@ -425,7 +428,7 @@ def propose_guided(logits, pmin, pmax, umin, A, nf, snr_coarse, umin_c, A_c, n_p
         ranges = [(0, nf)]
         if not fb:
             ranges = []
-            if pmax > PB_HI:
+            if search_long and pmax > PB_HI:
                 lo, hi = max(PB_HI, pmin), pmax
                 if hi > lo:
                     i0 = max(0, int(math.ceil(((1.0 / hi) ** (1.0 / 3.0) - umin) / A)))

@@ -23,7 +23,7 @@ EXPORTS = ("bls_default_params", "bls_plan_create", "bls_plan_query", "bls_plan_
            "bls_plan_frequencies", "bls_plan_durations", "bls_plan_upload", "bls_prepare", "bls_search_batch",
            "bls_snr", "bls_stats", "bls_run_noalloc", "bls_plan_destroy", "bls_status_string", "bls_limits", "bls_last_hip_error",
            # learned period proposal (include/mi355pp.h)
-           "pp_act_bytes", "pp_resample", "pp_forward", "pp_backward", "pp_adam", "pp_propose",
+           "pp_act_bytes", "pp_resample", "pp_forward", "pp_backward", "pp_adam", "pp_propose", "pp_propose_guided",
            "pp_tile_capacity", "pp_snr_windows")
 
 PP_NPARAM = 3122
@@ -135,6 +135,8 @@ def lib():
         L.pp_adam.argtypes = [vp, vp, vp, vp, i32, f32, vp]
         L.pp_propose.restype = i32
         L.pp_propose.argtypes = [vp, vp, vp, i32, f32, vp, vp, vp, vp, vp]
+        L.pp_propose_guided.restype = i32
+        L.pp_propose_guided.argtypes = [vp, vp, vp, i32, f32, i32, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp]
         L.pp_tile_capacity.restype = i32
         L.pp_tile_capacity.argtypes = [vp, ctypes.POINTER(i64)]
         L.pp_snr_windows.restype = i32

@@ -554,13 +554,16 @@ __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* 
 // their full grid and the fallback flag.
 // ----------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) k_propose(const StarDesc* __restrict__ stars, const float* __restrict__ logits,
-                                                int32_t topk, float conf, int64_t* __restrict__ windows,
-                                                uint8_t* __restrict__ fallback, float* __restrict__ conf_out,
-                                                int64_t* __restrict__ tiles) {
+                                                int32_t topk, float conf, int32_t search_long,
+                                                const StarDesc* __restrict__ cstars, const double* __restrict__ csnr,
+                                                int32_t n_peaks, int32_t halfwidth,
+                                                int64_t* __restrict__ windows, uint8_t* __restrict__ fallback,
+                                                float* __restrict__ conf_out, int64_t* __restrict__ tiles) {
   __shared__ uint8_t sel[kNpb];
   __shared__ double pr[kNpb + 1];
   __shared__ int64_t s_w0[PP_MAX_WINDOWS], s_w1[PP_MAX_WINDOWS], s_cum[PP_MAX_WINDOWS + 1];
-  __shared__ int s_nw;
+  __shared__ int64_t s_pick[PP_MAX_WINDOWS];
+  __shared__ int s_nw, s_fb, s_np;
   const int s = blockIdx.x, lane = threadIdx.x;
   const StarDesc d = stars[s];
   const float* z = logits + static_cast<int64_t>(s) * (kNpb + 1);
@@ -610,9 +613,6 @@ __global__ void __launch_bounds__(64) k_propose(const StarDesc* __restrict__ sta
     int nw = 0;
     auto emit = [&](int64_t i0, int64_t i1) {
       if (nw < PP_MAX_WINDOWS && i1 > i0) {
-        wo[3 * nw] = s;
-        wo[3 * nw + 1] = i0;
-        wo[3 * nw + 2] = i1;
         s_w0[nw] = i0;
         s_w1[nw] = i1;
         ++nw;
@@ -620,6 +620,7 @@ __global__ void __launch_bounds__(64) k_propose(const StarDesc* __restrict__ sta
     };
     const bool fb = !(c >= static_cast<double>(conf));
     fallback[s] = fb ? 1 : 0;
+    s_fb = fb ? 1 : 0;
     if (fb) {
       emit(0, d.nf);
     } else {
@@ -645,7 +646,92 @@ __global__ void __launch_bounds__(64) k_propose(const StarDesc* __restrict__ sta
           ++k;
         }
       }
-      if (d.pmax > kPbHi) range(kPbHi, d.pmax);
+      if (search_long && d.pmax > kPbHi) range(kPbHi, d.pmax);
+    }
+    s_nw = nw;
+    s_np = 0;
+  }
+  __syncthreads();
+  // Coarse-peak windows of a confident star: the n_peaks largest coarse S/N values,
+  // each blocking +-halfwidth coarse steps around it (ties to the lower index).
+  if (cstars && csnr && n_peaks > 0 && !s_fb) {
+    const StarDesc cd = cstars[s];
+    const double* v = csnr + cd.f_off;
+    const int64_t ncf = cd.nf;
+    for (int r = 0; r < n_peaks; ++r) {
+      double bv = -INFINITY;
+      int64_t bi = INT64_MAX;
+      for (int64_t i = lane; i < ncf; i += 64) {
+        bool blocked = false;
+        for (int q = 0; q < r; ++q) blocked |= (i - s_pick[q] <= halfwidth && s_pick[q] - i <= halfwidth);
+        if (blocked) continue;
+        const double x = v[i];
+        if (x > bv || (x == bv && i < bi) || bi == INT64_MAX) {
+          bv = x;
+          bi = i;
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int64_t oi = __shfl_xor(bi, o, 64);
+        if (oi != INT64_MAX && (bi == INT64_MAX || ov > bv || (ov == bv && oi < bi))) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if (bi == INT64_MAX) break;  // the coarse grid is exhausted
+      if (lane == 0) {
+        s_pick[r] = bi;
+        s_np = r + 1;
+      }
+      __syncthreads();
+    }
+    if (lane == 0) {
+      int nw = s_nw;
+      for (int r = 0; r < s_np; ++r) {
+        const int64_t lo = max<int64_t>(0, s_pick[r] - halfwidth), hi = min<int64_t>(ncf - 1, s_pick[r] + halfwidth);
+        const double a = ceil(((cd.umin + static_cast<double>(lo) * cd.A) - d.umin) / d.A);
+        const double e = floor(((cd.umin + static_cast<double>(hi) * cd.A) - d.umin) / d.A);
+        const int64_t i0 = a < 0.0 ? 0 : static_cast<int64_t>(a);
+        const int64_t i1 = e > static_cast<double>(d.nf - 1) ? d.nf - 1 : static_cast<int64_t>(e);
+        if (e >= 0.0 && i1 >= i0 && nw < PP_MAX_WINDOWS) {
+          s_w0[nw] = i0;
+          s_w1[nw] = i1 + 1;
+          ++nw;
+        }
+      }
+      // sorted, merged (overlapping or touching ranges join)
+      for (int q = 1; q < nw; ++q) {
+        const int64_t a0 = s_w0[q], a1 = s_w1[q];
+        int u = q - 1;
+        while (u >= 0 && (s_w0[u] > a0 || (s_w0[u] == a0 && s_w1[u] > a1))) {
+          s_w0[u + 1] = s_w0[u];
+          s_w1[u + 1] = s_w1[u];
+          --u;
+        }
+        s_w0[u + 1] = a0;
+        s_w1[u + 1] = a1;
+      }
+      int m = 0;
+      for (int q = 0; q < nw; ++q) {
+        if (m > 0 && s_w0[q] <= s_w1[m - 1]) {
+          s_w1[m - 1] = max(s_w1[m - 1], s_w1[q]);
+        } else {
+          s_w0[m] = s_w0[q];
+          s_w1[m] = s_w1[q];
+          ++m;
+        }
+      }
+      s_nw = m;
+    }
+  }
+  __syncthreads();
+  if (lane == 0) {
+    const int nw = s_nw;
+    for (int q = 0; q < nw; ++q) {
+      wo[3 * q] = s;
+      wo[3 * q + 1] = s_w0[q];
+      wo[3 * q + 2] = s_w1[q];
     }
     for (int q = nw; q < PP_MAX_WINDOWS; ++q) {
       wo[3 * q] = -1;
@@ -654,7 +740,6 @@ __global__ void __launch_bounds__(64) k_propose(const StarDesc* __restrict__ sta
     }
     s_cum[0] = 0;
     for (int q = 0; q < nw; ++q) s_cum[q + 1] = s_cum[q] + (s_w1[q] - s_w0[q] + d.per_tile - 1) / d.per_tile;
-    s_nw = nw;
   }
   __syncthreads();
   if (!tiles) return;
@@ -763,8 +848,29 @@ extern "C" bls_status pp_propose(const bls_plan* plan, void* ws, const float* d_
   if (plan->n_stars == 0) return BLS_OK;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const StarDesc* sd = reinterpret_cast<const StarDesc*>(static_cast<char*>(ws) + plan->layout.stars);
-  hipLaunchKernelGGL(k_propose, dim3(plan->n_stars), dim3(64), 0, st, sd, d_logits, topk, conf, d_windows,
+  hipLaunchKernelGGL(k_propose, dim3(plan->n_stars), dim3(64), 0, st, sd, d_logits, topk, conf, 1,
+                     static_cast<const StarDesc*>(nullptr), static_cast<const double*>(nullptr), 0, 0, d_windows,
                      d_fallback, d_conf, d_tiles);
+  BLS_HIP_TRY(hipGetLastError());
+  return BLS_OK;
+}
+
+extern "C" bls_status pp_propose_guided(const bls_plan* plan, void* ws, const float* d_logits, int32_t topk,
+                                        float conf, int32_t search_long, const bls_plan* coarse, void* coarse_ws,
+                                        const double* d_coarse_snr, int32_t n_peaks, int32_t halfwidth,
+                                        int64_t* d_windows, uint8_t* d_fallback, float* d_conf, int64_t* d_tiles,
+                                        bls_stream_t stream) {
+  if (!plan || !coarse || !d_logits || !d_coarse_snr || !d_windows || !d_fallback) return BLS_E_ARG;
+  if (topk < 0 || n_peaks < 0 || halfwidth < 0 || topk + 1 + n_peaks > PP_MAX_WINDOWS) return BLS_E_ARG;
+  if (coarse->n_stars != plan->n_stars) return BLS_E_ARG;
+  if (!ws_ready(plan, ws) || !ws_ready(coarse, coarse_ws)) return BLS_E_STATE;
+  if (plan->n_stars == 0) return BLS_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const StarDesc* sd = reinterpret_cast<const StarDesc*>(static_cast<char*>(ws) + plan->layout.stars);
+  const StarDesc* cd = reinterpret_cast<const StarDesc*>(static_cast<char*>(coarse_ws) + coarse->layout.stars);
+  hipLaunchKernelGGL(k_propose, dim3(plan->n_stars), dim3(64), 0, st, sd, d_logits, topk, conf, search_long, cd,
+                     d_coarse_snr,
+                     n_peaks, halfwidth, d_windows, d_fallback, d_conf, d_tiles);
   BLS_HIP_TRY(hipGetLastError());
   return BLS_OK;
 }

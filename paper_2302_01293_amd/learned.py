@@ -137,13 +137,19 @@ class LearnedSearch:
     inputs."""
 
     def __init__(self, batch, net: ProposalNet, params=None, coarse_factor: int = 16, topk: int = 8,
-                 conf: float = 0.9):
+                 conf: float = 0.9, coarse_peaks: int = 0, halfwidth: int = 3, search_long: bool = True):
+        """``coarse_peaks`` > 0: the windows of a confident star also cover that many
+        peaks of the coarse S/N spectrum (``pp_propose_guided``), each widened by
+        ``halfwidth`` coarse steps; ``search_long`` = False then drops the blanket
+        window over periods beyond the network's 100-d range."""
         p = params if params is not None else _lib.default_params()
         self.fine = DeviceSearch.from_batch(batch, p)
         cp = _lib.default_params(**{f: getattr(p, f) for f, _ in _lib.BlsParams._fields_})
         cp.spp = p.spp / coarse_factor
+        self.coarse_peaks, self.halfwidth = int(coarse_peaks), int(halfwidth)
+        self.search_long = bool(search_long)
         self.coarse = DeviceSearch(batch.t, batch.y, batch.w, batch.offsets, batch.rho, batch.pmin, batch.pmax,
-                                   cp, want_best=False, want_snr=False,
+                                   cp, want_best=False, want_snr=self.coarse_peaks > 0,
                                    inputs=(self.fine.t, self.fine.y, self.fine.w))
         self.net = net
         self.topk, self.conf = int(topk), float(conf)
@@ -163,12 +169,22 @@ class LearnedSearch:
         f, c = self.fine, self.coarse
         f.run_prepare(stream)
         c.run_prepare(stream)
+        if self.coarse_peaks > 0:
+            c.run_search(stream)
+            c.run_snr(stream)
         x, lag = resample(f, stream)
         self.logits = self.net.forward(x, lag, None, stream)
-        check("pp_propose", L.pp_propose(f.plan.h, f.ws_ptr, self.logits.data_ptr(), self.topk, self.conf,
-                                         self.windows.data_ptr(), self.fallback.data_ptr(),
-                                         self.confidence.data_ptr(), self.tiles.data_ptr(), h))
-        c.run_search(stream)
+        if self.coarse_peaks > 0:
+            check("pp_propose_guided", L.pp_propose_guided(
+                f.plan.h, f.ws_ptr, self.logits.data_ptr(), self.topk, self.conf, int(self.search_long),
+                c.plan.h, c.ws_ptr,
+                c.snr.data_ptr(), self.coarse_peaks, self.halfwidth, self.windows.data_ptr(),
+                self.fallback.data_ptr(), self.confidence.data_ptr(), self.tiles.data_ptr(), h))
+        else:
+            check("pp_propose", L.pp_propose(f.plan.h, f.ws_ptr, self.logits.data_ptr(), self.topk, self.conf,
+                                             self.windows.data_ptr(), self.fallback.data_ptr(),
+                                             self.confidence.data_ptr(), self.tiles.data_ptr(), h))
+            c.run_search(stream)
         f.run_search(stream, windows=self.tiles)
         check("pp_snr_windows", L.pp_snr_windows(f.plan.h, f.ws_ptr, f.sr.data_ptr(), f.best.data_ptr(),
                                                  c.plan.h, c.ws_ptr, c.sr.data_ptr(), self.windows.data_ptr(),

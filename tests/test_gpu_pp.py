@@ -10,6 +10,8 @@ relative tolerance of a few 10^-3.  Integer outputs (windows, fallback flags,
 indices) are compared exactly, range ends within one grid index (the cube root of
 the host library and of the device may differ in the last bit).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -17,6 +19,7 @@ from oracle import pp_oracle as P
 from paper_2302_01293_amd import synth
 
 pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _say(*a):
@@ -294,3 +297,96 @@ def test_learned_path_fallback_is_plain():
     assert np.array_equal(rl["i_snr"], rp["i_snr"])
     assert np.array_equal(rl["snr"].view(np.uint64), rp["snr"].view(np.uint64))
     assert abs(ls.searched_fraction() - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("search_long", [1, 0])
+def test_propose_guided_parity(oracle, search_long):
+    """pp_propose_guided against the oracle's propose_guided: the network's windows,
+    the coarse-peak windows and their merge, on stars whose coarse S/N spectrum has
+    planted peaks (and ties), with the tiled list covering exactly the windows."""
+    import ctypes
+
+    import torch
+    from paper_2302_01293_amd import _lib
+    from paper_2302_01293_amd.device import DeviceSearch
+    b = synth.ragged(8, start=170, max_sectors=13)
+    ds = DeviceSearch.from_batch(b)
+    cp = _lib.default_params()
+    cp.spp = cp.spp / 16
+    cs = DeviceSearch(b.t, b.y, b.w, b.offsets, b.rho, b.pmin, b.pmax, cp, want_best=False, want_snr=True,
+                      inputs=(ds.t, ds.y, ds.w))
+    S = b.n_stars
+    rng = np.random.default_rng(21)
+    z = rng.normal(0, 1, (S, P.NPB + 1))
+    for s in range(S):
+        if s % 4 != 3:
+            for k in rng.choice(P.NPB, 2, replace=False):
+                z[s, k] += 15.0
+    z = z.astype(np.float32)
+    snr_c = rng.normal(0, 1, cs.plan.n_freq)
+    for s in range(S):
+        a, e = int(cs.plan.freq_offsets[s]), int(cs.plan.freq_offsets[s + 1])
+        for k in rng.choice(e - a, 3, replace=False):
+            snr_c[a + k] = 20.0 + k % 2            # two may tie at 20
+    zd = torch.as_tensor(z).cuda()
+    sd = torch.as_tensor(snr_c).cuda()
+    win = torch.empty((S, _lib.PP_MAX_WINDOWS, 3), dtype=torch.int64, device="cuda")
+    fb = torch.empty(S, dtype=torch.uint8, device="cuda")
+    cf = torch.empty(S, dtype=torch.float32, device="cuda")
+    cap = ctypes.c_int64()
+    _lib.check("pp_tile_capacity", _lib.lib().pp_tile_capacity(ds.plan.h, ctypes.byref(cap)))
+    tiles = torch.empty((int(cap.value), 3), dtype=torch.int64, device="cuda")
+    npk, hw = 4, 3
+    _lib.check("pp_propose_guided", _lib.lib().pp_propose_guided(
+        ds.plan.h, ds.ws_ptr, zd.data_ptr(), 8, 0.9, search_long, cs.plan.h, cs.ws_ptr, sd.data_ptr(), npk, hw,
+        win.data_ptr(),
+        fb.data_ptr(), cf.data_ptr(), tiles.data_ptr(), 0))
+    torch.cuda.synchronize()
+    wg, fg, cg, tg = win.cpu().numpy(), fb.cpu().numpy(), cf.cpu().numpy(), tiles.cpu().numpy()
+    n_conf = 0
+    for s in range(S):
+        fi = ds.plan.star_info(s)
+        ci = cs.plan.star_info(s)
+        nf = int(fi["nf"])
+        a, e = int(cs.plan.freq_offsets[s]), int(cs.plan.freq_offsets[s + 1])
+        ro, co, fo = P.propose_guided(z[s].astype(np.float64), fi["pmin"], fi["pmax"], fi["umin"], fi["A"], nf,
+                                      snr_c[a:e], ci["umin"], ci["A"], npk, hw, search_long=bool(search_long))
+        rows = [tuple(r[1:]) for r in wg[s] if r[0] == s]
+        _say("star", s, "fallback", bool(fg[s]), "windows", rows)
+        assert bool(fg[s]) == fo and abs(cg[s] - co) <= 1e-5
+        # the network's bin-edge mapping may differ by one index (cbrt); coarse peaks are exact
+        assert len(rows) == len(ro), (rows, ro)
+        for (g0, g1), (o0, o1) in zip(rows, ro):
+            assert abs(g0 - o0) <= 1 and abs(g1 - o1) <= 1
+        if not fo:
+            n_conf += 1
+            for ic in P.coarse_peaks(snr_c[a:e], npk, hw):
+                i_f = int(round((ci["umin"] + ic * ci["A"] - fi["umin"]) / fi["A"]))
+                if 0 <= i_f < nf:
+                    assert any(g0 <= i_f < g1 for g0, g1 in rows), (s, ic, i_f)
+        cov_w = set()
+        for g0, g1 in rows:
+            cov_w.update(range(g0, g1))
+        cov_t = []
+        for r in tg[tg[:, 0] == s]:
+            cov_t.extend(range(r[1], r[2]))
+        assert set(cov_t) == cov_w and len(cov_t) == len(cov_w), s   # merged: no index searched twice
+    assert n_conf >= 3
+
+
+def test_guided_learned_path_recovers_sector_scale_detections():
+    """The guided learned path (network windows plus coarse-peak windows) on 64 stars
+    of the 1-26-sector recipe (seeds disjoint from the benchmark's): every plain
+    detection is reported again at its frequency index, while only a small part of
+    the fine grid is searched."""
+    import torch
+    from paper_2302_01293_amd import learned
+    b = synth.config4(64, start=200_000)
+    net = learned.ProposalNet(np.load(os.path.join(ROOT, "paper_2302_01293_amd", "pp_weights.npy")))
+    out, pres, lres = learned.time_paths(b, net, reps=1, topk=8, conf=0.5, coarse_peaks=2, search_long=False)
+    torch.cuda.synchronize()
+    _say("guided path on 64 sector-scale stars: recovery %d/%d, searched fraction %.4f, speed-up %.2fx"
+         % (out["recovered"], out["plain_detections"], out["searched_fraction"], out["speedup"]))
+    assert out["plain_detections"] >= 3
+    assert out["recovered"] == out["plain_detections"]
+    assert out["searched_fraction"] < 0.05

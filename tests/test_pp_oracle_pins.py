@@ -236,3 +236,21 @@ def test_guided_proposal_adds_the_coarse_peak_and_keeps_fallback():
     assert not fb3 and c3 > 0.99
     assert r3 == P.merge_ranges(P.coarse_windows(P.coarse_peaks(snr_c, 2, 3), umin, 16 * A, len(snr_c),
                                                  umin, A, nf, 3))
+
+
+def test_guided_proposal_without_the_long_period_window():
+    """With Pmax > 100 d the plain proposal adds [100 d, Pmax]; search_long=False drops
+    it and keeps the network's and the coarse peaks' windows."""
+    umin, A = (1.0 / 300.0) ** (1 / 3), 2e-5
+    nf = int(((1 / 0.35) ** (1 / 3) - umin) / A) + 1
+    z = np.full(P.NPB + 1, -5.0)
+    z[300] = 12.0
+    snr_c = np.zeros(nf // 16)
+    snr_c[2000] = 9.0
+    i_long = int(((1 / 100.0) ** (1 / 3) - umin) / A)        # fine index of P = 100 d
+    with_long, _, _ = P.propose_guided(z, 0.35, 300.0, umin, A, nf, snr_c, umin, 16 * A, 1, 3)
+    without, _, _ = P.propose_guided(z, 0.35, 300.0, umin, A, nf, snr_c, umin, 16 * A, 1, 3, search_long=False)
+    assert any(a == 0 and b >= i_long for a, b in with_long)          # [100 d, Pmax] starts at f0
+    assert not any(a <= 10 for a, b in without)
+    base, _, _ = P.propose(z, 0.35, 300.0, umin, A, nf, pb_hi_window=False)
+    assert without == P.merge_ranges(base + P.coarse_windows([2000], umin, 16 * A, len(snr_c), umin, A, nf, 3))
