@@ -59,10 +59,12 @@ def search_sources_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, key: dict):
+def measured_traffic(workload: str, key: dict, cells_per_launch: float):
     """HBM bytes per search call from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     runs (scaled by a plain copy's readings), if they were taken on this workload
-    (same batch shape) with the current kernel sources; else None."""
+    (same batch shape) with the current kernel sources; else None.  Runs that record
+    bytes per cell (a workload whose batches differ from step to step) are scaled to
+    the timed calls' mean cells."""
     try:
         with open(counters_path(workload)) as fh:
             c = json.load(fh)
@@ -70,6 +72,8 @@ def measured_traffic(workload: str, key: dict):
         return None
     if c.get("source_sha256") != search_sources_digest() or c.get("key") != key:
         return None
+    if "bytes_per_cell" in c:
+        return float(c["bytes_per_cell"]) * cells_per_launch
     return float(c["bytes_per_launch"])
 
 
@@ -369,7 +373,7 @@ def main():
     peak = FP64_OPS_PEAK / 1e12
     key = dict(workload=args.workload, batch_stars=args.batch_stars if args.workload == "cfg4" else None,
                stars=args.stars or None, precision=args.precision)
-    traffic = measured_traffic(args.workload, key)
+    traffic = measured_traffic(args.workload, key, cells / args.steps)
     out = {
         "metric": METRIC,
         "value": n_timed / (wall) * 3600.0,
