@@ -357,6 +357,31 @@ def main():
     log("per step ms (device): prepare %.3f search %.3f snr %.3f total %.3f; wall/step %.3f"
         % (prep.mean(), srch.mean(), snr.mean(), dev_ms.mean(), step_ms))
     results = [res_host[k].numpy().view(_lib.RESULT_DTYPE).copy() for k in range(args.steps)]
+    # Post-BLS statistics of the last step's batch (outside the timed step): per-star
+    # counts and criteria (bls_stats) and the trapezoid fit with noise and S/N_pink
+    # (bls_fit), timed with HIP events on the stream.
+    post = None
+    last = steps[(args.steps - 1) % n_batches]
+    if last.plan is not None:
+        nS = last.batch.n_stars
+        st_dev = torch.empty(nS * _lib.STATS_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        fit_dev = torch.empty(nS * _lib.FIT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        last.plan.stats(ws_ptr, last.t.data_ptr(), last.y.data_ptr(), last.w.data_ptr(), best.data_ptr(),
+                        res_dev.data_ptr(), st_dev.data_ptr(), 9.0, h)
+        e1.record(stream)
+        last.plan.fit(ws_ptr, last.t.data_ptr(), last.y.data_ptr(), last.w.data_ptr(), res_dev.data_ptr(),
+                      fit_dev.data_ptr(), 9.0, 9.0, h)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        fr = fit_dev.cpu().numpy().view(_lib.FIT_DTYPE)
+        post = {"stars": nS, "stats_ms": e0.elapsed_time(e1), "fit_ms": e1.elapsed_time(e2),
+                "candidates": int(fr["candidate"].sum()),
+                "fit_iterations_mean": float(fr["iterations"][fr["status"] == 0].mean())
+                if np.any(fr["status"] == 0) else 0.0}
+        log("post-BLS statistics of %d stars: bls_stats %.3f ms, bls_fit %.3f ms, %d candidates"
+            % (nS, post["stats_ms"], post["fit_ms"], post["candidates"]))
     n_inj = n_hit = 0
     for k in range(args.steps):
         b = steps[k % n_batches].batch
@@ -396,6 +421,7 @@ def main():
         "kernel_ms_per_step": {"prepare": float(prep.mean()), "search": float(srch.mean()),
                                "snr": float(snr.mean()), "device_total": float(dev_ms.mean())},
         "injections_recovered": [n_hit, n_inj],
+        "post_bls": post,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": "k_search (fold + boundary accumulation + scan; all launches of "

@@ -127,6 +127,30 @@ typedef struct bls_star_stats {
   int32_t status;      /* 0 ok; 1 no valid window at the detection frequency (counts 0) */
 } bls_star_stats;
 
+/* Trapezoid fit, noise and S/N_pink of a star's detection (Sec. 2.2 items 2-4) and
+ * the complete detection criteria, written by bls_fit(). */
+typedef struct bls_fit_result {
+  double t0;           /* fitted mid-transit time, days */
+  double depth;        /* fitted depth delta (flux; positive for a dip) */
+  double q;            /* fitted duration / period */
+  double q_in;         /* fitted ingress duration / duration, in [0, 0.5] */
+  double level;        /* fitted out-of-transit level z */
+  double chi2;         /* sum w (y - model)^2 over the fit points */
+  double sigma_w;      /* white noise: standard deviation of y - model (w > 0 points) */
+  double sigma_r;      /* red noise on the duration time scale */
+  double depth_eff;    /* depth integral over the duration / duration = depth (1 - q_in) */
+  double snr_pink;     /* depth_eff / sqrt(sigma_w^2 / n_t + sigma_r^2 / N_t) (Eq. 2);
+                          +inf without residual scatter */
+  int64_t n_fit;       /* points within two starting durations of mid-transit */
+  int64_t n_t;         /* points in transit (|t - mid-transit| < duration / 2) */
+  int64_t n_transits;  /* transits holding at least one of them */
+  int32_t iterations;  /* Levenberg-Marquardt iterations */
+  int32_t candidate;   /* 1: n_transits >= 2, snr_pink > pink_min and S/N > snr_min */
+  int32_t status;      /* 0 ok; 1 no detection to start from (needs d_best in bls_snr);
+                          2 no point within two durations */
+  int32_t pad;
+} bls_fit_result;
+
 typedef struct bls_plan bls_plan;
 
 /* Fill *p with the paper's parameters. */
@@ -216,6 +240,27 @@ bls_status bls_snr(bls_plan* plan, void* d_workspace, const double* d_sr, const 
 bls_status bls_stats(bls_plan* plan, void* d_workspace, const double* d_t, const double* d_y, const double* d_w,
                      const bls_best* d_best, const bls_result* d_result, double snr_min,
                      bls_star_stats* d_stats, bls_stream_t stream);
+
+/* Trapezoid fit of each star's detection and the statistics built on it (Sec. 2.2
+ * items 2-4; the note's detection criteria in the paragraph after that list).
+ * Starts from d_result (bls_snr with d_best: period, mid-transit time, duration and
+ * depth of the best-S/N window); the period stays fixed.  Fits T0, depth, q = duration
+ * / period, q_in = ingress / duration and the out-of-transit level z to the points
+ * (w > 0) within two starting durations of mid-transit, flux = z - depth s with s the
+ * trapezoid (1 in the flat bottom, linear ingress and egress, 0 outside), by
+ * weighted Levenberg-Marquardt (start q_in = 0.2, lambda 1e-3, x10 / /10, at most 60
+ * iterations, stop when a kept step lowers chi^2 by at most 1e-10 of it); q in
+ * [1e-6, 1], q_in in [0, 0.5].  Then, over every w > 0 point: sigma_w = standard
+ * deviation of y - model; sigma_r^2 = max(0, sigma_D^2 - sigma_w^2 / n_bar) from the
+ * scatter sigma_D of the mean residuals in bins of one fitted duration (n_bar points
+ * per non-empty bin); S/N_pink (Eq. 2) with the depth replaced by the trapezoid's mean
+ * depth over the duration.  candidate = (n_transits >= 2 && snr_pink > pink_min &&
+ * S/N > snr_min); the note uses 9 and 9.  Device inputs: the packed t, y, w (w
+ * nullable) given to bls_prepare and d_result [n_stars]; output d_fit [n_stars].
+ * Enqueued on stream; allocates nothing; deterministic (fixed reduction order). */
+bls_status bls_fit(bls_plan* plan, void* d_workspace, const double* d_t, const double* d_y, const double* d_w,
+                   const bls_result* d_result, double snr_min, double pink_min, bls_fit_result* d_fit,
+                   bls_stream_t stream);
 
 /* Release a plan (host memory only). */
 void bls_plan_destroy(bls_plan* plan);

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "BLS_OK", -1: "BLS_E_ARG", -2: "BLS_E_INPUT", -3: "BLS_E_EMPT
 
 EXPORTS = ("bls_default_params", "bls_plan_create", "bls_plan_query", "bls_plan_star_info",
            "bls_plan_frequencies", "bls_plan_durations", "bls_plan_upload", "bls_prepare", "bls_search_batch",
-           "bls_snr", "bls_stats", "bls_run_noalloc", "bls_plan_destroy", "bls_status_string", "bls_limits", "bls_last_hip_error",
+           "bls_snr", "bls_stats", "bls_fit", "bls_run_noalloc", "bls_plan_destroy", "bls_status_string", "bls_limits", "bls_last_hip_error",
            # learned period proposal (include/mi355pp.h)
            "pp_act_bytes", "pp_resample", "pp_forward", "pp_backward", "pp_adam", "pp_propose", "pp_propose_guided",
            "pp_tile_capacity", "pp_snr_windows")
@@ -55,7 +55,13 @@ RESULT_DTYPE = np.dtype([("i_snr", np.int64), ("i_sr", np.int64), ("period", np.
 STATS_DTYPE = np.dtype([("n_in", np.int64), ("n_before", np.int64), ("n_after", np.int64),
                         ("n_transits", np.int64), ("oot_level", np.float64), ("candidate", np.int32),
                         ("status", np.int32)])
+FIT_DTYPE = np.dtype([("t0", np.float64), ("depth", np.float64), ("q", np.float64), ("q_in", np.float64),
+                      ("level", np.float64), ("chi2", np.float64), ("sigma_w", np.float64),
+                      ("sigma_r", np.float64), ("depth_eff", np.float64), ("snr_pink", np.float64),
+                      ("n_fit", np.int64), ("n_t", np.int64), ("n_transits", np.int64),
+                      ("iterations", np.int32), ("candidate", np.int32), ("status", np.int32), ("pad", np.int32)])
 assert BEST_DTYPE.itemsize == 24 and RESULT_DTYPE.itemsize == 88 and STATS_DTYPE.itemsize == 48
+assert FIT_DTYPE.itemsize == 120
 
 _lib = None
 
@@ -112,6 +118,8 @@ def lib():
         L.bls_snr.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.bls_stats.restype = i32
         L.bls_stats.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp, vp]
+        L.bls_fit.restype = i32
+        L.bls_fit.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp]
         L.bls_run_noalloc.restype = i32
         L.bls_run_noalloc.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp]
         L.bls_plan_destroy.restype = None
@@ -267,6 +275,13 @@ class Plan:
                              stream or None)
         if st != BLS_OK:
             raise BlsError("bls_stats", st)
+
+    def fit(self, d_ws: int, d_t: int, d_y: int, d_w: int | None, d_result: int, d_fit: int,
+            snr_min: float = 9.0, pink_min: float = 9.0, stream: int = 0):
+        st = lib().bls_fit(self.h, d_ws, d_t, d_y, d_w or None, d_result, float(snr_min), float(pink_min), d_fit,
+                           stream or None)
+        if st != BLS_OK:
+            raise BlsError("bls_fit", st)
 
     def run_noalloc(self, d_t: int, d_y: int, d_w: int | None, d_sr: int, d_best: int | None,
                     d_snr: int | None, d_result: int, d_windows: int | None = None, n_windows: int = 0,

@@ -47,6 +47,7 @@ class DeviceSearch:
         self.snr = torch.empty(nf, dtype=torch.float64, device=dev) if want_snr else None
         self.result = torch.empty(self.plan.n_stars * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
         self.stats = None
+        self.fit = None
         self.plan.upload(self.ws_ptr, self.plan.workspace_bytes, _stream_handle())
 
     @classmethod
@@ -86,6 +87,19 @@ class DeviceSearch:
         self.plan.stats(self.ws_ptr, self.t.data_ptr(), self.y.data_ptr(),
                         None if self.w is None else self.w.data_ptr(), self.best.data_ptr(),
                         self.result.data_ptr(), self.stats.data_ptr(), snr_min, stream=_stream_handle(stream))
+
+    def run_fit(self, snr_min: float = 9.0, pink_min: float = 9.0, stream=None):
+        """Trapezoid fit, noise, S/N_pink and the detection criteria at each star's
+        detection (``bls_fit``; starts from the results of ``run_snr`` with best windows)."""
+        if self.fit is None:
+            self.fit = torch.empty(self.plan.n_stars * _lib.FIT_DTYPE.itemsize, dtype=torch.uint8,
+                                   device=self.device)
+        self.plan.fit(self.ws_ptr, self.t.data_ptr(), self.y.data_ptr(),
+                      None if self.w is None else self.w.data_ptr(), self.result.data_ptr(), self.fit.data_ptr(),
+                      snr_min, pink_min, stream=_stream_handle(stream))
+
+    def fit_host(self) -> np.ndarray:
+        return self.fit.cpu().numpy().view(_lib.FIT_DTYPE)
 
     def stats_host(self) -> np.ndarray:
         return self.stats.cpu().numpy().view(_lib.STATS_DTYPE)
