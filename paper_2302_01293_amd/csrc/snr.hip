@@ -11,10 +11,10 @@
 //
 // One workgroup per star: 256 threads when every spectrum of the batch is short
 // (the selections are bound by their barriers, so several small groups per CU beat
-// one large one), else 1024.  Medians are exact order
-// statistics found by an 8-bit
-// radix select on the FP64 bit patterns (an order-preserving integer key), with
-// the counting done in an LDS histogram.
+// one large one), else 1024.  Medians are exact order statistics on an
+// order-preserving integer key of the FP64 values (select.hpp): a key-range pass,
+// histogram passes (buckets sized to the keys left) until the rank's bucket is
+// small, and a gather of that bucket, ranked in LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
