@@ -246,6 +246,9 @@ def main():
                          "windows guided by that many peaks of the coarse S/N spectrum, no blanket window "
                          "beyond 100 d; topk 0: no network windows); the first is the headline")
     ap.add_argument("--no-ceilings", action="store_true", help="skip the unit-rate microbenchmarks")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default schedule instead of tuning it on the first batch")
+    ap.add_argument("--tune-sample", type=int, default=48, help="stars of the first batch the autotuner times")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size kernel "
                          "for scaling the profiler's FETCH_SIZE / WRITE_SIZE counters)")
@@ -279,6 +282,20 @@ def main():
     params = _lib.default_params(precision=args.precision)
     if args.precision:
         desc += ", packed reduced-precision sums"
+    tuned = None
+    if not args.no_autotune:
+        # Schedule (work-item size, per-item frequency cap, large-shape threshold)
+        # by coordinate descent on a stratified sample of the first batch, before the
+        # clock; results do not depend on it.
+        from paper_2302_01293_amd import autotune
+        t_tune = time.perf_counter()
+        tuned = autotune.tune(batches[0], params, n_sample=args.tune_sample, reps=2, use_cache=False,
+                              axes=("tile_cells", "item_freqs", "big_points"))
+        for k in ("tile_cells", "item_freqs", "big_points"):
+            setattr(params, k, int(tuned[k]))
+        tuned["seconds"] = time.perf_counter() - t_tune
+        log("autotuned schedule: tile_cells %d, item_freqs %d, big_points %d (%.1f s)"
+            % (tuned["tile_cells"], tuned["item_freqs"], tuned["big_points"], tuned["seconds"]))
 
     # Every batch's light curves go to HBM before the clock starts.
     steps = [Step(b, dev) for b in batches]
@@ -422,6 +439,8 @@ def main():
                                "snr": float(snr.mean()), "device_total": float(dev_ms.mean())},
         "injections_recovered": [n_hit, n_inj],
         "post_bls": post,
+        "schedule": None if tuned is None else {k: tuned[k] for k in ("tile_cells", "item_freqs", "big_points",
+                                                                       "times_ms", "seconds")},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": "k_search (fold + boundary accumulation + scan; all launches of "

@@ -80,6 +80,12 @@ typedef struct bls_params {
   int64_t tile_cells;  /* target points x frequencies per work item; 0 = library default
                           (6 Mi cells and at most 128 frequencies per item); an
                           autotuner may pick another (results do not change) */
+  int64_t big_points;  /* stars with more points search every frequency in the large
+                          workgroup shape (fewer point re-reads); 0 = 100,000 (results
+                          do not change) */
+  int32_t item_freqs;  /* most frequencies per work item; 0 = 128, or 4096 when
+                          tile_cells is set (results do not change) */
+  int32_t reserved;    /* 0 */
 } bls_params;
 
 /* Per-star inputs. */

@@ -1,13 +1,20 @@
-"""Autotuner for the search's work-item size.
+"""Autotuner of the search's schedule.
 
-The plan cuts every star's frequency grid into work items of about ``tile_cells``
-points x frequencies; the persistent search kernel pulls them in cost order.  Small
-items balance the tail of a launch, large ones amortise each item's set-up (grid
-descriptors, point loads per frequency group).  The best size depends on the
-device and on the batch shape, so it is measured: each candidate is timed on a
-sample of the batch's stars (device time of ``bls_search_batch``, median of a few
-launches) and the winner is cached per device and batch shape in a JSON file.
-The tile size never changes results, only speed.
+Three run-time choices of the plan change only speed, never results:
+  * ``tile_cells``: points x frequencies per work item.  The persistent search
+    kernel pulls items in cost order; small items balance the tail of a launch,
+    large ones amortise each item's set-up (grid descriptors, point loads per
+    frequency group);
+  * ``item_freqs``: the most frequencies per item (short stars spread over more
+    items, and the groups of an XCD share fewer stars' points in its L2);
+  * ``big_points``: stars with more points take the large workgroup shape (72 KB
+    accumulator window, two groups per CU) for every frequency instead of the common
+    one (48 KB, three per CU): fewer point re-reads per frequency against less
+    latency hiding.
+The best values depend on the device and on the batch shape, so they are measured:
+coordinate descent over the three axes, each candidate timed on a stratified sample
+of the batch's stars (device time of ``bls_search_batch``, median of a few
+launches), the winners cached per device and batch shape in a JSON file.
 """
 from __future__ import annotations
 
@@ -18,6 +25,8 @@ import os
 import numpy as np
 
 CANDIDATES = (1 << 20, 3 << 19, 3 << 20, 6 << 20, 12 << 20, 24 << 20)
+ITEM_FREQS = (64, 128, 256, 1024)
+BIG_POINTS = (50_000, 100_000, 200_000, 1 << 40)
 
 
 def default_cache_path() -> str:
@@ -60,42 +69,65 @@ def sample_stars(points: np.ndarray, n: int, seed: int = 0) -> np.ndarray:
     return np.unique(picks)
 
 
+def _time_search(sub, params, reps: int) -> float:
+    import torch
+    from .device import DeviceSearch
+    ds = DeviceSearch.from_batch(sub, params, want_snr=False, want_best=False)
+    ds.run_prepare()
+    ds.run_search()  # warm-up
+    stream = torch.cuda.current_stream()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ds.run_search()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del ds
+    return float(np.median(ms))
+
+
 def tune(batch, params=None, candidates=CANDIDATES, n_sample: int = 256, reps: int = 3,
-         cache_path: str | None = None, use_cache: bool = True) -> dict:
-    """Pick ``tile_cells`` for a batch; returns {"tile_cells", "times_ms", "key", "cached"}."""
+         cache_path: str | None = None, use_cache: bool = True, axes=("tile_cells",),
+         item_freqs=ITEM_FREQS, big_points=BIG_POINTS, log=None) -> dict:
+    """Pick the schedule for a batch by coordinate descent over ``axes`` (any of
+    "tile_cells", "item_freqs", "big_points", tuned in that order, each with the
+    others at their current picks); returns {"tile_cells", "item_freqs",
+    "big_points", "times_ms", "key", "cached"} (0 = library default)."""
     import torch
     from . import _lib
-    from .device import DeviceSearch
 
     points = np.diff(np.asarray(batch.offsets))
-    key = shape_key(torch.cuda.get_device_name(), points)
+    key = shape_key(torch.cuda.get_device_name(), points) + "|" + ",".join(axes)
     path = cache_path or default_cache_path()
     cache = load_cache(path) if use_cache else {}
     if use_cache and key in cache:
-        return dict(tile_cells=int(cache[key]["tile_cells"]), times_ms=cache[key].get("times_ms", {}),
-                    key=key, cached=True)
+        c = cache[key]
+        return dict(tile_cells=int(c["tile_cells"]), item_freqs=int(c.get("item_freqs", 0)),
+                    big_points=int(c.get("big_points", 0)), times_ms=c.get("times_ms", {}), key=key,
+                    cached=True)
     sub = batch.subset(sample_stars(points, n_sample))
+    base = params if params is not None else _lib.default_params()
+    pick = dict(tile_cells=int(base.tile_cells), item_freqs=int(base.item_freqs), big_points=int(base.big_points))
+    grid = dict(tile_cells=candidates, item_freqs=item_freqs, big_points=big_points)
     times = {}
-    for c in candidates:
-        p = params if params is not None else _lib.default_params()
-        p = _lib.default_params(**{f: getattr(p, f) for f, _ in _lib.BlsParams._fields_})
-        p.tile_cells = int(c)
-        ds = DeviceSearch.from_batch(sub, p, want_snr=False, want_best=False)
-        ds.run_prepare()
-        ds.run_search()  # warm-up
-        stream = torch.cuda.current_stream()
-        ms = []
-        for _ in range(reps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            ds.run_search()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms.append(e0.elapsed_time(e1))
-        times[str(c)] = float(np.median(ms))
-        del ds
-    best = int(min(times, key=lambda k: times[k]))
+    for ax in ("tile_cells", "item_freqs", "big_points"):
+        if ax not in axes:
+            continue
+        res = {}
+        for c in grid[ax]:
+            p = _lib.default_params(**{f: getattr(base, f) for f, _ in _lib.BlsParams._fields_})
+            for k, v in pick.items():
+                setattr(p, k, int(v))
+            setattr(p, ax, int(c))
+            res[str(c)] = _time_search(sub, p, reps)
+            if log:
+                log("autotune %s = %d: %.2f ms" % (ax, c, res[str(c)]))
+        pick[ax] = int(min(res, key=lambda k: res[k]))
+        times[ax] = res
+    out = dict(pick, times_ms=times, key=key, cached=False)
     if use_cache:
-        cache[key] = dict(tile_cells=best, times_ms=times)
+        cache[key] = dict(pick, times_ms=times)
         save_cache(path, cache)
-    return dict(tile_cells=best, times_ms=times, key=key, cached=False)
+    return out

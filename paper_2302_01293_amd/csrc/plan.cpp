@@ -69,7 +69,8 @@ double gap_threshold(const StarDesc& d, double f, int32_t noverlap) {
 bool valid_params(const bls_params& p) {
   return p.spp > 0.0 && p.qmin_fac > 0.0 && p.qmax_fac >= p.qmin_fac && p.dlogq > 0.0 &&
          p.noverlap >= 1 && p.a_min_rstar > 0.0 && p.sector_days > 0.0 &&
-         (p.precision == 0 || p.precision == 1) && p.tile_cells >= 0 && std::isfinite(p.spp) &&
+         (p.precision == 0 || p.precision == 1) && p.tile_cells >= 0 && p.big_points >= 0 &&
+         p.item_freqs >= 0 && p.item_freqs <= (1 << 20) && std::isfinite(p.spp) &&
          std::isfinite(p.qmin_fac) && std::isfinite(p.qmax_fac) && std::isfinite(p.dlogq);
 }
 
@@ -134,6 +135,7 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
   for (int32_t m : ladder) mask |= 1u << (m - 1);
   plan->consts.m_mask = mask;
   plan->consts.packed = p->precision == 1 ? 1 : 0;
+  plan->consts.big_points = p->big_points > 0 ? p->big_points : kBigPoints;
   try {
     plan->stars.resize(n_stars);
     plan->freq_offsets.assign(n_stars + 1, 0);
@@ -215,7 +217,7 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
     d.nf = static_cast<int64_t>(steps) + 1;
     d.nb0 = nbins_at(d, 0, p->noverlap);
     if (d.nb0 > kNbWide || d.nb0 < 1) return fail(BLS_E_UNSUPPORTED);
-    if (d.nb0 > kNbLimit || d.n > kBigPoints) plan->has_big = true;
+    if (d.nb0 > kNbLimit || d.n > plan->consts.big_points) plan->has_big = true;
     if (d.nb0 > kNbLimitBig) plan->has_wide = true;
     const int32_t sturges =
         static_cast<int32_t>(std::floor(1.0 + 3.322 * std::log10(static_cast<double>(d.nf)) + 0.5));
@@ -267,7 +269,7 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
       int64_t per = std::max<int64_t>(32, target_cells / std::max<int64_t>(1, d.n));
       // the default also caps an item at 128 frequencies: short stars then spread
       // over more items, and the groups working on one XCD share fewer stars' points
-      per = std::min<int64_t>(per, p->tile_cells > 0 ? 4096 : 128);
+      per = std::min<int64_t>(per, p->item_freqs > 0 ? p->item_freqs : (p->tile_cells > 0 ? 4096 : 128));
       plan->stars[s].per_tile = static_cast<int32_t>(per);
       plan->stars[s].tile_off = plan->tile_capacity;
       plan->tile_capacity += (d.nf + per - 1) / per + kWindowSlack;

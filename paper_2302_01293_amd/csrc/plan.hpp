@@ -34,7 +34,7 @@ constexpr int kNbLimit = kGBytes / 16 - 32;        // largest fine-bin count of 
                                                     // shape (16 B per bin, plus the
                                                     // replicated wrap bins): 3040
 constexpr int kNbLimitBig = kGBytesBig / 16 - 32;  // of the large shape: 4576
-constexpr int64_t kBigPoints = 100000;  // stars with more points take the large shape
+constexpr int64_t kBigPoints = 100000;  // default: stars with more points take the large shape
                                        // for all their frequencies (fewer point
                                        // re-reads per frequency)
 constexpr int kNbWide = (1 << 20) - 1;       // largest fine-bin count (window start bins
@@ -99,6 +99,7 @@ struct Consts {
   int32_t m_max;       // longest duration in bins
   uint32_t m_mask;     // bit (m-1) set for every duration m of the ladder
   int32_t packed;      // 1: weights and residuals share one int64 per point (precision 1)
+  int64_t big_points;  // stars with more points take the large shape for every frequency
 };
 
 struct Layout {  // byte offsets inside the device workspace

@@ -843,7 +843,7 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
 // keep the register allocation of the common case free of the second form.
 // DIP: only windows with s < 0 (dips) count.  BIG: the large workgroup shape, for
 // the frequencies whose fine-bin count lies in (kNbLimit, kNbLimitBig] and for every
-// frequency up to kNbLimitBig bins of stars with more than kBigPoints points.
+// frequency up to kNbLimitBig bins of stars with more than big_points points.
 template <bool PACKED, bool DFORM, bool DIP, bool BIG>
 __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search(SearchArgs a) {
   using W = Win<BIG>;
@@ -872,7 +872,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
     if ((ng > kGapLanes) != DFORM) continue;  // the other launch's item
     // Long stars take the large shape for every frequency; the others only for
     // frequencies with more fine bins than the common shape holds.
-    const bool long_star = d.n > kBigPoints;
+    const bool long_star = d.n > a.c.big_points;
     if (!BIG && long_star) continue;
     const StarRt rt = a.rt[it.star];
     const double w_unit = PACKED ? packed_w_unit(rt) : 0.0;  // packed: 1 / quantised total weight

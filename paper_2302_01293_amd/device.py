@@ -124,6 +124,15 @@ class DeviceSearch:
         torch.cuda.current_stream().wait_stream(side)
         return g
 
+    def capture_pipeline(self):
+        """One HIP graph for the whole device path of this plan: the copies of t, y, w
+        from pinned host buffers, prepare -> search -> S/N, and the copy of the
+        per-star results back to a pinned host buffer.  Fill ``pipe.y_host`` (and, with
+        the same first and last weighted times per star, ``w_host``) with new values,
+        call ``pipe.replay()`` and read ``pipe.results()``: a serving loop over new
+        fluxes of the same stars without per-call launches or allocations."""
+        return _Pipeline(self)
+
     # ---- host copies ----
     def sr_host(self) -> np.ndarray:
         return self.sr.cpu().numpy()
@@ -140,3 +149,34 @@ class DeviceSearch:
     def star_slice(self, s: int) -> slice:
         fo = self.plan.freq_offsets
         return slice(int(fo[s]), int(fo[s + 1]))
+
+
+class _Pipeline:
+    """Pinned host staging buffers and the captured graph of ``capture_pipeline``."""
+
+    def __init__(self, ds: DeviceSearch):
+        self.ds = ds
+        self.t_host = ds.t.cpu().pin_memory()
+        self.y_host = ds.y.cpu().pin_memory()
+        self.w_host = None if ds.w is None else ds.w.cpu().pin_memory()
+        self.result_host = torch.empty(ds.result.numel(), dtype=torch.uint8, pin_memory=True)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(self.graph, stream=side):
+            ds.t.copy_(self.t_host, non_blocking=True)
+            ds.y.copy_(self.y_host, non_blocking=True)
+            if ds.w is not None:
+                ds.w.copy_(self.w_host, non_blocking=True)
+            ds.run()
+            self.result_host.copy_(ds.result, non_blocking=True)
+        torch.cuda.current_stream().wait_stream(side)
+
+    def replay(self):
+        self.graph.replay()
+
+    def results(self) -> np.ndarray:
+        """Per-star results of the last replay (waits for it)."""
+        torch.cuda.synchronize()
+        return self.result_host.numpy().view(RESULT_DTYPE).copy()

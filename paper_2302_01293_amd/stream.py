@@ -33,8 +33,10 @@ def _pinned(a: np.ndarray) -> torch.Tensor:
     return t
 
 
-def run_stream(batches, params=None, log=None):
-    """Search an iterable of ``synth.Batch``; returns (list of result arrays, stats)."""
+def run_stream(batches, params=None, log=None, autotune_first: bool = False):
+    """Search an iterable of ``synth.Batch``; returns (list of result arrays, stats).
+    ``autotune_first``: tune the schedule (``autotune.tune``, all three axes) on the
+    first batch and use it for every batch; the picks are in stats["schedule"]."""
     dev = torch.device("cuda")
     copy_stream = torch.cuda.Stream()
     compute = torch.cuda.current_stream()
@@ -44,7 +46,17 @@ def run_stream(batches, params=None, log=None):
     cells = 0.0
     t0 = time.perf_counter()
     pending = []
+    schedule = None
     for bi, b in enumerate(batches):
+        if bi == 0 and autotune_first:
+            from . import autotune
+            base = params if params is not None else _lib.default_params()
+            schedule = autotune.tune(b, base, n_sample=48, reps=2, use_cache=False,
+                                     axes=("tile_cells", "item_freqs", "big_points"))
+            params = _lib.default_params(**{f: getattr(base, f) for f, _ in _lib.BlsParams._fields_})
+            for k in ("tile_cells", "item_freqs", "big_points"):
+                setattr(params, k, int(schedule[k]))
+            t0 = time.perf_counter()       # the clock starts after tuning
         slot = slots[bi % 2]
         if slot.done is not None:          # the slot's previous batch must be finished
             slot.done.synchronize()
@@ -84,5 +96,6 @@ def run_stream(batches, params=None, log=None):
             slot.done.synchronize()
             results[slot.index] = slot.result_host.numpy().view(_lib.RESULT_DTYPE).copy()
     wall = time.perf_counter() - t0
-    return [results[i] for i in sorted(results)], dict(stars=n_stars, cells=cells, wall_s=wall, stars_per_hour=n_stars / wall * 3600.0,
-                         cells_per_s=cells / wall)
+    return [results[i] for i in sorted(results)], dict(stars=n_stars, cells=cells, wall_s=wall,
+                                                       stars_per_hour=n_stars / wall * 3600.0,
+                                                       cells_per_s=cells / wall, schedule=schedule)

@@ -40,6 +40,38 @@ def test_graph_replay_matches_eager():
         torch.cuda.synchronize()
 
 
+def test_pipeline_graph_with_copies_matches_eager():
+    """H2D copies -> prepare -> search -> S/N -> D2H copy captured as one graph and
+    replayed for three different flux vectors of the same stars (eager work and
+    synchronisations between the replays): each replay's results equal an eager run
+    of the same data."""
+    import torch
+    from paper_2302_01293_amd.device import DeviceSearch
+    b = synth.ragged(6, start=75)
+    _say("case pipeline graph: 6 ragged stars, three flux vectors")
+    ds = DeviceSearch.from_batch(b)
+    ds.run()
+    torch.cuda.synchronize()
+    pipe = ds.capture_pipeline()
+    rng = np.random.default_rng(3)
+    other = pu.run_gpu(synth.ragged(2, start=70))
+    for rep in range(3):
+        y = b.y + rng.normal(0, 5e-4, len(b.y))
+        if rep == 1:
+            y[(b.t - b.t[0]) % 2.7 < 0.1] -= 4e-3     # a planted dip in every star
+        pipe.y_host.numpy()[...] = y
+        pipe.replay()
+        got = pipe.results()
+        eager = DeviceSearch(b.t, y, b.w, b.offsets, b.rho, b.pmin, b.pmax)
+        eager.run()
+        torch.cuda.synchronize()
+        exp = eager.results_host()
+        assert np.array_equal(got.view(np.uint8), exp.view(np.uint8)), rep
+        _say("replay", rep, "best periods", np.round(got["period"], 4).tolist())
+        other.run()
+        torch.cuda.synchronize()
+
+
 def test_windows_match_full_grid():
     import torch
     b = synth.ragged(5, start=80)
@@ -116,6 +148,31 @@ def test_autotune_picks_a_candidate_and_results_do_not_change(tmp_path):
         ds = pu.run_gpu(b, _lib.default_params(tile_cells=c))
         assert np.array_equal(ds.sr_host().view(np.uint64), ref.sr_host().view(np.uint64)), c
         assert np.array_equal(ds.results_host(), ref.results_host()), c
+
+
+def test_autotune_three_axes_results_do_not_change(tmp_path):
+    """Coordinate descent over the work-item size, the per-item frequency cap and the
+    point count above which a star takes the large workgroup shape, on stars of 1-13
+    sectors (some above 50,000 points): every candidate gives bit-identical spectra,
+    best windows and results."""
+    import torch
+    from paper_2302_01293_amd import autotune, _lib
+    b = synth.config2(12, start=500)
+    pts = np.diff(b.offsets)
+    _say("case autotune, three axes: points per star", pts.tolist())
+    assert pts.max() > 50_000
+    out = autotune.tune(b, candidates=(1 << 20, 6 << 20), n_sample=12, reps=1, cache_path=str(tmp_path / "t.json"),
+                        axes=("tile_cells", "item_freqs", "big_points"), item_freqs=(64, 512),
+                        big_points=(50_000, 1 << 40))
+    _say("picks", {k: out[k] for k in ("tile_cells", "item_freqs", "big_points")})
+    assert out["item_freqs"] in (64, 512) and out["big_points"] in (50_000, 1 << 40)
+    ref = pu.run_gpu(b)
+    for kw in (dict(item_freqs=64), dict(item_freqs=512), dict(big_points=50_000), dict(big_points=1 << 40),
+               dict(tile_cells=1 << 20, item_freqs=4096, big_points=30_000)):
+        ds = pu.run_gpu(b, _lib.default_params(**kw))
+        assert np.array_equal(ds.sr_host().view(np.uint64), ref.sr_host().view(np.uint64)), kw
+        assert np.array_equal(ds.best_host(), ref.best_host()), kw
+        assert np.array_equal(ds.results_host(), ref.results_host()), kw
 
 
 @pytest.mark.parametrize("precision", [0, 1])
