@@ -49,9 +49,46 @@ def labelled(batch, chunk: int = 2048):
     return torch.cat(xs), torch.cat(lags), np.concatenate(labels), np.concatenate(res)
 
 
-def evaluate(batch, net, tag: str, conf: float = 0.9, topk: int = 8):
+def labelled_streamed(make, n: int, start: int, chunk: int, threads: int):
+    """Generate, label and resample n light curves in chunks (``make(count, start)``
+    builds a batch): only the network inputs (16 KB per light curve, on the device)
+    and the labels are kept, so the light curves never need to fit in memory at once.
+    Generation of the next chunk (threads on the host) overlaps the labelling of the
+    current one on the GPU."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    from . import learned, synth
+
+    def gen(s0):
+        cnt = min(chunk, n - s0)
+        per = (cnt + threads - 1) // threads
+        with ThreadPoolExecutor(threads) as ex:
+            parts = list(ex.map(lambda k: make(min(per, cnt - k * per), start + s0 + k * per),
+                                [k for k in range(threads) if k * per < cnt]))
+        return synth.concat(parts)
+
+    xs, lags, labels = [], [], []
+    t0 = time.time()
+    with ThreadPoolExecutor(1) as pool:
+        fut = pool.submit(gen, 0)
+        for s0 in range(0, n, chunk):
+            b = fut.result()
+            if s0 + chunk < n:
+                fut = pool.submit(gen, s0 + chunk)
+            x, lag, lab, _ = learned.labelled_inputs(b)
+            torch.cuda.synchronize()
+            xs.append(x)
+            lags.append(lag)
+            labels.append(lab)
+            log("labelled %d / %d light curves (%d periods so far, %.0f s)"
+                % (s0 + b.n_stars, n, int(sum((l >= 0).sum() for l in labels)), time.time() - t0))
+            del b
+    return torch.cat(xs), torch.cat(lags), np.concatenate(labels)
+
+
+def evaluate(batch, net, tag: str, conf: float = 0.9, topk: int = 8, reps: int = 3):
     from . import learned
-    out, _, _ = learned.time_paths(batch, net, conf=conf, topk=topk)
+    out, _, _ = learned.time_paths(batch, net, reps=reps, conf=conf, topk=topk)
     log("%s: recovery %d/%d = %.4f, exact index %d, fallback %.3f, searched %.3f, plain %.1f ms, "
         "learned %.1f ms, speed-up %.2fx" % (tag, out["recovered"], out["plain_detections"], out["recovery"],
                                               out["exact_index"], out["fallback_fraction"],
@@ -75,6 +112,10 @@ def main(argv=None):
     ap.add_argument("--recipe", choices=("cfg3", "mixed"), default="cfg3")
     ap.add_argument("--out", default="")
     ap.add_argument("--report", default="")
+    ap.add_argument("--stream-chunk", type=int, default=0,
+                    help="generate and label the training set in chunks of this many light curves (cfg3 recipe)")
+    ap.add_argument("--threads", type=int, default=8, help="host threads generating light curves")
+    ap.add_argument("--eval-reps", type=int, default=3)
     args = ap.parse_args(argv)
 
     import torch
@@ -88,29 +129,38 @@ def main(argv=None):
         train = synth.concat([synth.config3(half, start=0, max_sectors=args.max_sectors),
                               synth.config1(args.n_train - half, start=CFG1_TRAIN_START)])
         eval1 = synth.config1(args.n_eval, start=CFG1_EVAL_START)
-    else:
+    elif not args.stream_chunk:
         train = synth.config3(args.n_train, start=0, max_sectors=args.max_sectors)
-    log("generated %d + %d light curves (%.1f s)" % (train.n_stars, evalb.n_stars, time.time() - t0))
     t1 = time.time()
-    x, lag, labels, _ = labelled(train)
+    if args.stream_chunk:
+        if args.recipe != "cfg3":
+            raise SystemExit("--stream-chunk supports the cfg3 recipe")
+        x, lag, labels = labelled_streamed(
+            lambda c, st: synth.config3(c, start=st, max_sectors=args.max_sectors), args.n_train, 0,
+            args.stream_chunk, args.threads)
+        n_train = args.n_train
+    else:
+        log("generated %d + %d light curves (%.1f s)" % (train.n_stars, evalb.n_stars, time.time() - t0))
+        x, lag, labels, _ = labelled(train)
+        n_train = train.n_stars
     log("labelled by the plain search: %d periods, %d null (%.1f s)" % ((labels >= 0).sum(), (labels < 0).sum(),
                                                                         time.time() - t1))
     net = learned.ProposalNet(seed=args.seed)
-    before = evaluate(evalb, net, "untrained", args.conf)
+    before = evaluate(evalb, net, "untrained", args.conf, reps=args.eval_reps)
     t2 = time.time()
     hist = learned.train(net, x, lag, labels, epochs=args.epochs, batch=args.batch, lr=args.lr, seed=args.seed,
                          log=log)
     torch.cuda.synchronize()
     log("trained %d steps (%.1f s)" % (net.step, time.time() - t2))
-    after = evaluate(evalb, net, "trained", args.conf, args.topk)
+    after = evaluate(evalb, net, "trained", args.conf, args.topk, reps=args.eval_reps)
     sweep = {}
     for c in [float(v) for v in args.sweep.split(",") if v]:
-        sweep[str(c)] = evaluate(evalb, net, "trained, conf %.3f" % c, c, args.topk)
+        sweep[str(c)] = evaluate(evalb, net, "trained, conf %.3f" % c, c, args.topk, reps=args.eval_reps)
     sweep1 = {}
     if eval1 is not None:
         for c in [args.conf] + [float(v) for v in args.sweep.split(",") if v]:
             sweep1[str(c)] = evaluate(eval1, net, "trained, one-sector boxes, conf %.3f" % c, c, args.topk)
-    rep = dict(n_train=train.n_stars, n_eval=evalb.n_stars, max_sectors=args.max_sectors, epochs=args.epochs,
+    rep = dict(n_train=n_train, n_eval=evalb.n_stars, max_sectors=args.max_sectors, epochs=args.epochs,
                batch=args.batch, lr=args.lr, conf=args.conf, steps=net.step, loss_first=hist[0],
                loss_last=hist[-1], label_periods=int((labels >= 0).sum()), untrained=before, trained=after, sweep=sweep,
                topk=args.topk, recipe=args.recipe, sweep_one_sector=sweep1)
