@@ -50,9 +50,11 @@ typedef struct {
   int32_t noverlap;   /* shifted bin sets per shortest duration (3) */
   int32_t dip_only;   /* 1: only windows with s < 0 count */
   int32_t mad_of_raw; /* 1: sigma from the MAD of raw SR instead of the residual */
-  int32_t pad_;
+  int32_t exact_duration; /* 1: exact circular duration asin(R_star / a) P / pi, else small-angle */
   double a_min;       /* minimum a/R* (2) */
   double sector_days; /* gap length that splits continuous stretches (27.4) */
+  int32_t rebin;      /* 1: one bin set per duration of a continuous ladder */
+  int32_t pad_;
 } orc_params;
 
 /* Per-star bounds and grid description. */
@@ -102,6 +104,18 @@ double orc_qcirc(double f, double rho) {
   double u = cbrt(f);
   return orc_krho(rho) * (u * u);
 }
+
+/* The same without the small-angle step: a central transit of a circular orbit
+ * spans the orbital angle 2 theta with sin theta = R_star / a, so q =
+ * asin(R_star / a) / pi, and R_star / a = pi q_small.  R_star / a above 1 (periods
+ * below contact, only through an explicit minimum period) is clamped to 1. */
+static double orc_exact_from_small(double qs) {
+  double x = ORC_PI * qs;
+  if (x > 1.0) x = 1.0;
+  return asin(x) / ORC_PI;
+}
+
+double orc_qcirc_exact(double f, double rho) { return orc_exact_from_small(orc_qcirc(f, rho)); }
 
 /* ------------------------------------------------------------------------- */
 /* Period bounds (Sec. 2.1).                                                  */
@@ -174,9 +188,19 @@ static double orc_freq(const orc_bounds_t* b, int64_t i, double* uu_out) {
   return uu * u;
 }
 
-static int32_t orc_nbins(const orc_bounds_t* b, const orc_params* p, double uu) {
+/* Shortest searched duty cycle at grid point uu = u^2: qmin_fac times the circular
+ * one, small-angle (kq uu, kq = qmin_fac krho) or exact; the exact one is never
+ * taken below the small-angle one (asin x >= x), so it never needs more bins. */
+static double orc_qlo(const orc_bounds_t* b, const orc_params* p, double uu) {
   double kq = p->qmin_fac * b->krho;
-  return (int32_t)ceil((double)p->noverlap / (kq * uu));
+  double qs = kq * uu;
+  if (!p->exact_duration) return qs;
+  double qe = p->qmin_fac * orc_exact_from_small(b->krho * uu);
+  return qe > qs ? qe : qs;
+}
+
+static int32_t orc_nbins(const orc_bounds_t* b, const orc_params* p, double uu) {
+  return (int32_t)ceil((double)p->noverlap / orc_qlo(b, p, uu));
 }
 
 int64_t orc_grid(const orc_bounds_t* b, const orc_params* p, double* f, int32_t* nb, int64_t cap) {
@@ -210,6 +234,26 @@ int32_t orc_durations(const orc_params* p, int32_t* m_out, int32_t cap) {
     ++cnt;
   }
   return cnt;
+}
+
+/* Continuous duration ladder of the per-duration rebinning (rebin = 1): factors
+ * g_k = min(e^(k dlogq), qmax/qmin) for k = 0..ceil(ln(qmax/qmin)/dlogq), so that
+ * q_k = g_k q_lo runs from the shortest to the longest searched duration in steps
+ * of dlogq in ln q (Sec. 2.1 footnote). */
+int32_t orc_rebin_ladder(const orc_params* p, double* g_out, int32_t cap) {
+  int32_t kmax = (int32_t)ceil(log(p->qmax_fac / p->qmin_fac) / p->dlogq);
+  double gcap = p->qmax_fac / p->qmin_fac;
+  if (kmax + 1 > cap) return ORC_E_ARG;
+  for (int32_t k = 0; k <= kmax; ++k) {
+    double e = exp((double)k * p->dlogq);
+    g_out[k] = e < gcap ? e : gcap;
+  }
+  return kmax + 1;
+}
+
+/* Bins of the k-th bin set: ceil(noverlap / q_k), q_k = q_lo g_k. */
+static int32_t orc_rebin_nb(double qlo, double g, int32_t noverlap) {
+  return (int32_t)ceil((double)noverlap / (qlo * g));
 }
 
 /* ------------------------------------------------------------------------- */
@@ -329,6 +373,86 @@ static void orc_bls_freq(const orc_norm* d, double f, int32_t nb, const int32_t*
   *s_out = bs;
 }
 
+/* Per-duration rebinning at one frequency (rebin = 1; the literal reading of the
+ * cuvarbase parameters, Sec. 2.1 footnote): for each duration q_k of the continuous
+ * ladder the phase circle gets its own nb_k = ceil(noverlap / q_k) bins, and the
+ * windows are noverlap consecutive bins (cyclic) starting at every bin, i.e.
+ * noverlap shifted bin sets of width about q_k.  Bin b = min(nb_k - 1,
+ * floor(phase nb_k)); a window is valid when noverlap < nb_k and 0 < r < 1 (s < 0
+ * with dip_only); ties go to the smallest (k, j).  Outputs: SR, k (in m), j, r, s
+ * and the winning set's nb_k (nb_0 when no window is valid). */
+static void orc_bls_freq_rebin(const orc_norm* d, double f, double qlo, const double* g, int32_t ng,
+                               int32_t noverlap, int32_t dip_only, double* hw, double* hs, double* sr_out,
+                               int32_t* k_out, int32_t* j_out, double* r_out, double* s_out,
+                               int32_t* nb_out) {
+  double best = -1.0, br = 0.0, bs = 0.0;
+  int32_t bk = 0, bj = -1, bnb = orc_rebin_nb(qlo, g[0], noverlap);
+  for (int32_t k = 0; k < ng; ++k) {
+    int32_t nb = orc_rebin_nb(qlo, g[k], noverlap);
+    if (noverlap >= nb) continue;
+    for (int32_t b = 0; b < nb; ++b) hw[b] = hs[b] = 0.0;
+    for (int64_t q = 0; q < d->n; ++q) {
+      double ph = d->dt[q] * f;
+      ph = ph - floor(ph);
+      int32_t bin = (int32_t)floor(ph * (double)nb);
+      if (bin >= nb) bin = nb - 1;
+      hw[bin] += d->wt[q];
+      hs[bin] += d->wx[q];
+    }
+    for (int32_t j = 0; j < nb; ++j) {
+      double r = 0.0, s = 0.0;
+      for (int32_t u = 0; u < noverlap; ++u) {
+        int32_t c = (j + u) % nb;
+        r += hw[c];
+        s += hs[c];
+      }
+      if (!(r > 0.0 && r < 1.0)) continue;
+      if (dip_only && !(s < 0.0)) continue;
+      double pw = (s * s) / (r * (1.0 - r));
+      if (pw > best) {
+        best = pw;
+        bk = k;
+        bj = j;
+        br = r;
+        bs = s;
+        bnb = nb;
+      }
+    }
+  }
+  *sr_out = best >= 0.0 ? sqrt(best) : 0.0;
+  *k_out = bk;
+  *j_out = bj;
+  *r_out = br;
+  *s_out = bs;
+  *nb_out = bnb;
+}
+
+/* One grid frequency of a star in the configured mode; hw/hs hold nb_0 values. */
+static void orc_search_at(const orc_norm* d, const orc_bounds_t* b, const orc_params* p, int64_t i,
+                          const int32_t* mlist, int32_t nm, const double* g, int32_t ng, double* hw,
+                          double* hs, orc_spectrum* out, int64_t o) {
+  double uu;
+  double f = orc_freq(b, i, &uu);
+  out->f[o] = f;
+  if (p->rebin) {
+    orc_bls_freq_rebin(d, f, orc_qlo(b, p, uu), g, ng, p->noverlap, p->dip_only, hw, hs, out->sr + o,
+                       out->m + o, out->j + o, out->r + o, out->s + o, out->nb + o);
+  } else {
+    int32_t nb = orc_nbins(b, p, uu);
+    out->nb[o] = nb;
+    orc_bls_freq(d, f, nb, mlist, nm, p->dip_only, hw, hs, out->sr + o, out->m + o, out->j + o,
+                 out->r + o, out->s + o);
+  }
+}
+
+/* Largest bin count the search uses at grid point i (the k = 0 set when rebinning). */
+static int32_t orc_nb_needed(const orc_bounds_t* b, const orc_params* p, int64_t i, const double* g) {
+  double uu;
+  (void)orc_freq(b, i, &uu);
+  if (p->rebin) return orc_rebin_nb(orc_qlo(b, p, uu), g[0], p->noverlap);
+  return orc_nbins(b, p, uu);
+}
+
 int orc_bls_star(const double* t, const double* y, const double* w, int64_t n, double rho,
                  const orc_params* p, double pmin_override, double pmax_override,
                  orc_spectrum* out, int64_t cap, orc_bounds_t* bounds_out) {
@@ -341,29 +465,22 @@ int orc_bls_star(const double* t, const double* y, const double* w, int64_t n, d
   int32_t mlist[64];
   int32_t nm = orc_durations(p, mlist, 64);
   if (nm <= 0) return ORC_E_ARG;
+  double g[64];
+  int32_t ng = orc_rebin_ladder(p, g, 64);
+  if (ng <= 0) return ORC_E_ARG;
   orc_norm d;
   st = orc_normalise(t, y, w, n, b.t0, &d);
   if (st != ORC_OK) return st;
 
-  int32_t nb_max = 0;
+  int32_t nb_max = 1;
   for (int64_t i = 0; i < b.nf; ++i) {
-    double uu;
-    (void)orc_freq(&b, i, &uu);
-    int32_t nbi = orc_nbins(&b, p, uu);
+    int32_t nbi = orc_nb_needed(&b, p, i, g);
     if (nbi > nb_max) nb_max = nbi;
   }
   double* hw = (double*)malloc(sizeof(double) * (size_t)nb_max);
   double* hs = (double*)malloc(sizeof(double) * (size_t)nb_max);
 
-  for (int64_t i = 0; i < b.nf; ++i) {
-    double uu;
-    double f = orc_freq(&b, i, &uu);
-    int32_t nb = orc_nbins(&b, p, uu);
-    out->f[i] = f;
-    out->nb[i] = nb;
-    orc_bls_freq(&d, f, nb, mlist, nm, p->dip_only, hw, hs, out->sr + i, out->m + i, out->j + i,
-                 out->r + i, out->s + i);
-  }
+  for (int64_t i = 0; i < b.nf; ++i) orc_search_at(&d, &b, p, i, mlist, nm, g, ng, hw, hs, out, i);
   free(hw);
   free(hs);
   orc_norm_free(&d);
@@ -385,27 +502,20 @@ int orc_bls_star_at(const double* t, const double* y, const double* w, int64_t n
   int32_t mlist[64];
   int32_t nm = orc_durations(p, mlist, 64);
   if (nm <= 0) return ORC_E_ARG;
+  double g[64];
+  int32_t ng = orc_rebin_ladder(p, g, 64);
+  if (ng <= 0) return ORC_E_ARG;
   orc_norm d;
   st = orc_normalise(t, y, w, n, b.t0, &d);
   if (st != ORC_OK) return st;
   int32_t nb_max = 1;
   for (int64_t q = 0; q < k; ++q) {
-    double uu;
-    (void)orc_freq(&b, idx[q], &uu);
-    int32_t nbi = orc_nbins(&b, p, uu);
+    int32_t nbi = orc_nb_needed(&b, p, idx[q], g);
     if (nbi > nb_max) nb_max = nbi;
   }
   double* hw = (double*)malloc(sizeof(double) * (size_t)nb_max);
   double* hs = (double*)malloc(sizeof(double) * (size_t)nb_max);
-  for (int64_t q = 0; q < k; ++q) {
-    double uu;
-    double f = orc_freq(&b, idx[q], &uu);
-    int32_t nb = orc_nbins(&b, p, uu);
-    out->f[q] = f;
-    out->nb[q] = nb;
-    orc_bls_freq(&d, f, nb, mlist, nm, p->dip_only, hw, hs, out->sr + q, out->m + q, out->j + q,
-                 out->r + q, out->s + q);
-  }
+  for (int64_t q = 0; q < k; ++q) orc_search_at(&d, &b, p, idx[q], mlist, nm, g, ng, hw, hs, out, q);
   free(hw);
   free(hs);
   orc_norm_free(&d);
@@ -581,7 +691,8 @@ int orc_batch_run(int32_t S, const int64_t* offsets, const double* t, const doub
     orc_snr(f + fo, sr + fo, nf, p, snr ? snr + fo : NULL, trend ? trend + fo : NULL, &sres);
     int64_t i = sres.i_snr;
     double fi = f[fo + i];
-    int32_t mi = m[fo + i], ji = j[fo + i], nbi = nb[fo + i];
+    /* rebinning: m holds the duration index; the window is noverlap bins of nb */
+    int32_t mi = p->rebin ? p->noverlap : m[fo + i], ji = j[fo + i], nbi = nb[fo + i];
     double ri = r[fo + i], si = s_out[fo + i];
     R[0] = (double)sres.i_snr;
     R[1] = (double)sres.i_sr;

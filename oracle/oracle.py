@@ -42,15 +42,17 @@ class Params(ctypes.Structure):
         ("noverlap", ctypes.c_int32),
         ("dip_only", ctypes.c_int32),
         ("mad_of_raw", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("exact_duration", ctypes.c_int32),
         ("a_min", ctypes.c_double),
         ("sector_days", ctypes.c_double),
+        ("rebin", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
     ]
 
 
 def params(**kw) -> Params:
     p = Params(spp=2.0, qmin_fac=0.5, qmax_fac=2.0, dlogq=0.1, noverlap=3, dip_only=0,
-               mad_of_raw=0, pad_=0, a_min=2.0, sector_days=27.4)
+               mad_of_raw=0, exact_duration=0, a_min=2.0, sector_days=27.4, rebin=0, pad_=0)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -96,6 +98,10 @@ def lib():
         L.orc_period_at_a.argtypes = [d, d]
         L.orc_qcirc.restype = d
         L.orc_qcirc.argtypes = [d, d]
+        L.orc_qcirc_exact.restype = d
+        L.orc_qcirc_exact.argtypes = [d, d]
+        L.orc_rebin_ladder.restype = i32
+        L.orc_rebin_ladder.argtypes = [ctypes.POINTER(Params), vp, i32]
         L.orc_bounds.restype = ctypes.c_int
         L.orc_bounds.argtypes = [vp, vp, i64, d, ctypes.POINTER(Params), d, d, ctypes.POINTER(Bounds)]
         L.orc_grid.restype = i64
@@ -151,6 +157,21 @@ def period_at_a(a_min: float, rho: float = 1.0) -> float:
 
 def qcirc(f: float, rho: float = 1.0) -> float:
     return lib().orc_qcirc(f, rho)
+
+
+def qcirc_exact(f: float, rho: float = 1.0) -> float:
+    return lib().orc_qcirc_exact(f, rho)
+
+
+def rebin_ladder(p: Params | None = None) -> np.ndarray:
+    """Factors g_k of the continuous duration ladder (q_k = g_k q_lo) of the
+    per-duration rebinning."""
+    p = p or params()
+    out = np.zeros(64)
+    n = lib().orc_rebin_ladder(ctypes.byref(p), _ptr(out), 64)
+    if n < 0:
+        raise ValueError("bad duration parameters")
+    return out[:n].copy()
 
 
 def sturges(n: int) -> int:
