@@ -85,6 +85,18 @@ typedef struct bls_params {
                           do not change) */
   int32_t item_freqs;  /* most frequencies per work item; 0 = 128, or 4096 when
                           tile_cells is set (results do not change) */
+  int32_t exact_duration; /* 0: circular duration (P / pi)(R* / a), the small-angle
+                          form (default); 1: (P / pi) asin(R* / a), the exact central
+                          transit of a circular orbit (Sec. 2.1): only the fine-bin
+                          count nb changes (the frequency grid keeps the small-angle
+                          spacing, which is the finer one) */
+  int32_t rebin;       /* 0: one fine-bin set per frequency, windows of m bins from the
+                          duration ladder (default); 1: one bin set per duration of a
+                          continuous ladder q_k = min(e^(k dlogq), qmax/qmin) q_lo
+                          (k = 0..ceil(ln(qmax/qmin)/dlogq)) with nb_k =
+                          ceil(noverlap / q_k) bins and windows of noverlap bins
+                          (the literal reading of the noverlap parameter, Sec. 2.1
+                          footnote); bls_best.m then holds k.  Needs precision 0. */
   int32_t reserved;    /* 0 */
 } bls_params;
 
@@ -98,7 +110,9 @@ typedef struct bls_star {
 
 /* Best window at one frequency: m bins starting at fine bin j (start phase j/nb);
  * r = in-window weight fraction, s = in-window sum of w~ (y - ybar).
- * m = 0, j = -1 when no window is valid (then SR = 0). */
+ * m = 0, j = -1 when no window is valid (then SR = 0).  With rebin = 1, m is the
+ * duration index k and the window is noverlap bins of that duration's bin set
+ * (nb_k bins), starting at its bin j. */
 typedef struct bls_best {
   int32_t m, j;
   double r, s;
@@ -186,7 +200,11 @@ bls_status bls_plan_query(const bls_plan* plan, int64_t* n_freq_total, int64_t* 
 bls_status bls_plan_star_info(const bls_plan* plan, int32_t star, double* out10);
 
 /* Frequencies (1/day) and fine-bin counts of one star's grid, exactly as the
- * device computes them (f_host [nf], nb_host [nf], both host, nullable). */
+ * device computes them (f_host [nf], nb_host [nf], both host, nullable).  With
+ * exact_duration the count goes through asin, the host's libm here and the device
+ * math library there; the two can differ in the last place, which changes nb only
+ * where noverlap / q_lo lies within that of an integer.  With rebin, nb is the
+ * count of the k = 0 bin set (the largest). */
 bls_status bls_plan_frequencies(const bls_plan* plan, int32_t star, double* f_host, int32_t* nb_host);
 
 /* The fine-bin duration ladder: writes up to cap lengths, returns the count

@@ -40,7 +40,8 @@ class BlsParams(ctypes.Structure):
                 ("mad_of_raw", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("a_min_rstar", ctypes.c_double), ("sector_days", ctypes.c_double),
                 ("tile_cells", ctypes.c_int64), ("big_points", ctypes.c_int64),
-                ("item_freqs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("item_freqs", ctypes.c_int32), ("exact_duration", ctypes.c_int32),
+                ("rebin", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class BlsStar(ctypes.Structure):

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmi355bls.so")
-SOURCES = ["plan.cpp", "search.hip", "snr.hip", "pp.hip", "stats.hip", "fit.hip", "noalloc.hip"]
+SOURCES = ["plan.cpp", "search.hip", "rebin.hip", "snr.hip", "pp.hip", "stats.hip", "fit.hip", "noalloc.hip"]
 ARCH = os.environ.get("MI355BLS_ARCH", "gfx950")
 
 

@@ -25,7 +25,6 @@ namespace {
 constexpr double kGmSun = 1.3271244e20;  // m^3 s^-2 (IAU 2015 nominal)
 constexpr double kRSun = 6.957e8;        // m (IAU 2015 nominal)
 constexpr double kDay = 86400.0;         // s
-constexpr double kPi = 3.14159265358979323846;
 
 // Circular-orbit duty cycle coefficient of the Sun: the central transit of a
 // circular orbit lasts (P/pi)(R/a); with Kepler's third law, in days,
@@ -48,7 +47,9 @@ double period_at_a(double a_min, double rho) {
   return ((2.0 * kPi) * std::sqrt((a3 * r3) / (kGmSun * density(rho)))) / kDay;
 }
 
-int32_t nbins_at(const StarDesc& d, int64_t i, int32_t noverlap) {
+// Small-angle fine-bin count: an upper bound of every mode's count (the exact
+// duration is never shorter), used for the launch decisions.
+int32_t nbins_small(const StarDesc& d, int64_t i, int32_t noverlap) {
   const double u = d.umin + static_cast<double>(i) * d.A;
   const double uu = u * u;
   return static_cast<int32_t>(std::ceil(static_cast<double>(noverlap) / (d.kq * uu)));
@@ -70,7 +71,8 @@ bool valid_params(const bls_params& p) {
   return p.spp > 0.0 && p.qmin_fac > 0.0 && p.qmax_fac >= p.qmin_fac && p.dlogq > 0.0 &&
          p.noverlap >= 1 && p.a_min_rstar > 0.0 && p.sector_days > 0.0 &&
          (p.precision == 0 || p.precision == 1) && p.tile_cells >= 0 && p.big_points >= 0 &&
-         p.item_freqs >= 0 && p.item_freqs <= (1 << 20) && std::isfinite(p.spp) &&
+         p.item_freqs >= 0 && p.item_freqs <= (1 << 20) && (p.exact_duration == 0 || p.exact_duration == 1) &&
+         (p.rebin == 0 || p.rebin == 1) && std::isfinite(p.spp) &&
          std::isfinite(p.qmin_fac) && std::isfinite(p.qmax_fac) && std::isfinite(p.dlogq);
 }
 
@@ -121,6 +123,10 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
   if (!valid_params(*p)) return BLS_E_ARG;
   const std::vector<int32_t> ladder = duration_ladder(*p);
   if (ladder.empty() || ladder.back() > kMCap) return BLS_E_UNSUPPORTED;
+  // per-duration rebinning: exact int64 sums only, at most kRebinMax durations
+  const int32_t n_rebin = static_cast<int32_t>(std::ceil(std::log(p->qmax_fac / p->qmin_fac) / p->dlogq)) + 1;
+  if (p->rebin && (p->precision != 0 || n_rebin > kRebinMax || n_rebin < 1 || p->noverlap > kMCap))
+    return BLS_E_UNSUPPORTED;
 
   bls_plan* plan = new (std::nothrow) bls_plan();
   if (!plan) return BLS_E_NOMEM;
@@ -136,6 +142,18 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
   plan->consts.m_mask = mask;
   plan->consts.packed = p->precision == 1 ? 1 : 0;
   plan->consts.big_points = p->big_points > 0 ? p->big_points : kBigPoints;
+  plan->consts.exact_q = p->exact_duration ? 1 : 0;
+  plan->consts.rebin = p->rebin ? 1 : 0;
+  plan->consts.qmin_fac = p->qmin_fac;
+  if (p->rebin) {
+    // q_k / q_lo = min(e^(k dlogq), qmax/qmin), k = 0..n_rebin-1 (host libm exp)
+    const double gcap = p->qmax_fac / p->qmin_fac;
+    plan->consts.n_rebin = n_rebin;
+    for (int32_t k = 0; k < n_rebin; ++k) {
+      const double e = std::exp(static_cast<double>(k) * p->dlogq);
+      plan->consts.rebin_g[k] = e < gcap ? e : gcap;
+    }
+  }
   try {
     plan->stars.resize(n_stars);
     plan->freq_offsets.assign(n_stars + 1, 0);
@@ -215,10 +233,14 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
     const double steps = std::floor((umax - umin) / d.A);
     if (!(steps >= 0.0) || steps > 2.0e9) return fail(steps >= 0.0 ? BLS_E_UNSUPPORTED : BLS_E_EMPTY_GRID);
     d.nf = static_cast<int64_t>(steps) + 1;
-    d.nb0 = nbins_at(d, 0, p->noverlap);
-    if (d.nb0 > kNbWide || d.nb0 < 1) return fail(BLS_E_UNSUPPORTED);
-    if (d.nb0 > kNbLimit || d.n > plan->consts.big_points) plan->has_big = true;
-    if (d.nb0 > kNbLimitBig) plan->has_wide = true;
+    const int32_t nb_up = nbins_small(d, 0, p->noverlap);
+    {
+      const double u0 = d.umin;
+      d.nb0 = fine_bins(d, plan->consts, u0 * u0);
+    }
+    if (nb_up > kNbWide || d.nb0 < 1) return fail(BLS_E_UNSUPPORTED);
+    if (nb_up > kNbLimit || d.n > plan->consts.big_points) plan->has_big = true;
+    if (nb_up > kNbLimitBig) plan->has_wide = true;
     const int32_t sturges =
         static_cast<int32_t>(std::floor(1.0 + 3.322 * std::log10(static_cast<double>(d.nf)) + 0.5));
     d.sturges = std::max(1, std::min(sturges, kMaxSturges));
@@ -353,7 +375,10 @@ extern "C" bls_status bls_plan_frequencies(const bls_plan* plan, int32_t star, d
   const StarDesc& d = plan->stars[star];
   for (int64_t i = 0; i < d.nf; ++i) {
     if (f) f[i] = freq_at(d, i);
-    if (nb) nb[i] = nbins_at(d, i, plan->params.noverlap);
+    if (nb) {
+      const double u = d.umin + static_cast<double>(i) * d.A;
+      nb[i] = fine_bins(d, plan->consts, u * u);
+    }
   }
   return BLS_OK;
 }

@@ -8,6 +8,9 @@
 // with the same IEEE operations as the host (no FMA contraction anywhere).
 #pragma once
 
+#include <hip/hip_runtime.h>
+
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
@@ -45,6 +48,7 @@ constexpr int kGapLanes = 64;         // stars with more gap points fold in diff
 constexpr int kMCap = 32;             // longest duration (in fine bins)
 constexpr int64_t kMaxPoints = int64_t(1) << 30;
 constexpr int kMaxSturges = 64;
+constexpr int kRebinMax = 32;         // most durations of the per-duration rebinning ladder
 constexpr int kWindowSlack = 16;      // extra tiles per star in a tiled window list (one
                                       // per disjoint window: a window adds at most one
                                       // partial tile)
@@ -100,7 +104,40 @@ struct Consts {
   uint32_t m_mask;     // bit (m-1) set for every duration m of the ladder
   int32_t packed;      // 1: weights and residuals share one int64 per point (precision 1)
   int64_t big_points;  // stars with more points take the large shape for every frequency
+  int32_t exact_q;     // 1: exact circular duration (asin) for the shortest searched one
+  int32_t rebin;       // 1: one bin set per duration of the continuous ladder
+  int32_t n_rebin;     // durations of that ladder
+  int32_t pad_;
+  double qmin_fac;
+  double rebin_g[kRebinMax];  // q_k / q_lo of the ladder (host libm exp, as the oracle's)
 };
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Shortest searched duty cycle at grid point uu = u^2 (Sec. 2.1): qmin_fac times
+// the central circular-orbit duty cycle, small-angle (kq uu) or, with exact
+// durations, qmin_fac asin(R*/a) / pi with R*/a = pi krho uu (clamped to 1), never
+// taken below the small-angle value (so it never needs more bins).  The same IEEE
+// operations on host and device; asin is the host's libm or the device's math
+// library (the two can differ in the last place).
+__host__ __device__ inline double qlo_at(const StarDesc& d, const Consts& c, double uu) {
+  const double qs = d.kq * uu;
+  if (!c.exact_q) return qs;
+  double x = kPi * (d.krho * uu);
+  if (x > 1.0) x = 1.0;
+  const double qe = c.qmin_fac * (asin(x) / kPi);
+  return qe > qs ? qe : qs;
+}
+
+// Fine bins at grid point uu: the fewest bins of width at most q_lo / noverlap.
+__host__ __device__ inline int32_t fine_bins(const StarDesc& d, const Consts& c, double uu) {
+  return static_cast<int32_t>(ceil(static_cast<double>(c.noverlap) / qlo_at(d, c, uu)));
+}
+
+// Bins of the k-th set of the per-duration rebinning: ceil(noverlap / (q_lo g_k)).
+__host__ __device__ inline int32_t rebin_bins(double qlo, double g, int32_t noverlap) {
+  return static_cast<int32_t>(ceil(static_cast<double>(noverlap) / (qlo * g)));
+}
 
 struct Layout {  // byte offsets inside the device workspace
   int64_t stars, rt, items, gaps, gap_steps, dt, cw, cs, rho, counter, total;
@@ -109,6 +146,17 @@ struct Layout {  // byte offsets inside the device workspace
 // Records the HIP error code of a failed HIP call (per thread) and returns
 // BLS_E_HIP; bls_last_hip_error() reads it back.
 bls_status hip_failed(int hip_error_code);
+
+}  // namespace mi355bls
+
+struct bls_plan;
+
+namespace mi355bls {
+
+// The per-duration rebinning search (rebin = 1) over the plan's work items or a
+// caller's (star, i0, i1) list; `base` is the uploaded and prepared workspace.
+bls_status rebin_search(const bls_plan* plan, const char* base, const int64_t* d_windows, int64_t n_items,
+                        double* d_sr, bls_best* d_best, hipStream_t stream);
 
 }  // namespace mi355bls
 

@@ -38,12 +38,11 @@
 
 namespace mi355bls {
 
-__device__ __forceinline__ void grid_point(const StarDesc& d, int64_t i, int32_t noverlap, double& f,
-                                           int32_t& nb) {
+__device__ __forceinline__ void grid_point(const StarDesc& d, int64_t i, const Consts& c, double& f, int32_t& nb) {
   const double u = d.umin + static_cast<double>(i) * d.A;
   const double uu = u * u;
   f = uu * u;
-  nb = static_cast<int32_t>(ceil(static_cast<double>(noverlap) / (d.kq * uu)));
+  nb = fine_bins(d, c, uu);
 }
 
 // Fine bin of a point: b = min(nb-1, floor(frac(dt f) nb)).
@@ -562,7 +561,7 @@ __device__ bool next_item(const SearchArgs& a, GroupLds* g, int& queue, int& pro
       if (tid < 64) {
         double f;
         int32_t nb;
-        grid_point(d, it.i1 - 1, a.c.noverlap, f, nb);
+        grid_point(d, it.i1 - 1, a.c, f, nb);
         const double thr = 0.99 / (static_cast<double>(a.c.noverlap) * cbrt(f) / d.kq + f);
         const int c = count_at_least(a.gap_steps + d.g_off, d.n_gaps, thr);
         if (tid == 0) g->item[1] = c;
@@ -647,7 +646,7 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
   const int64_t n = d.n;
   double f;
   int32_t nb;
-  grid_point(d, fi, a.c.noverlap, f, nb);
+  grid_point(d, fi, a.c, f, nb);
   const double nbd = static_cast<double>(nb);
   const int32_t blast = fold_bin_nc(dt_last, f, nbd);
   const int mlim = min(m_max, nb - 1);
@@ -859,7 +858,6 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
   const int T = kSearchThreads;
   const int m_max = a.c.m_max;
   const uint32_t m_mask = a.c.m_mask;
-  const int32_t noverlap = a.c.noverlap;
 
   int queue = static_cast<int>(blockIdx.x % kXcds);  // used by thread 0 only
   int probes = 0;
@@ -884,7 +882,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
     {
       double f_first;
       int32_t nb_first;
-      grid_point(d, it.i0, noverlap, f_first, nb_first);
+      grid_point(d, it.i0, a.c, f_first, nb_first);
       if (nb_first > kNbWide || nb_first < 1) continue;  // rejected by the plan
     }
 
@@ -921,20 +919,22 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
       // group lets long ranges take more frequencies per group as nb shrinks.
       double f_g;
       int32_t nb_cap;
-      grid_point(d, g0, noverlap, f_g, nb_cap);
+      grid_point(d, g0, a.c, f_g, nb_cap);
       if (nb_cap > W::nb_hi) {  // searched by the large shape or k_search_wide
         F = 1;
         continue;
       }
       if (BIG && !long_star && nb_cap <= W::nb_lo) break;  // nb falls with frequency: the rest are the common shape's
-      int stride = __builtin_amdgcn_readfirstlane(nb_cap + m_max);
+      // with exact durations the count goes through the device asin, which need not
+      // be monotone in its last place: one bin of room for a later frequency's count
+      int stride = __builtin_amdgcn_readfirstlane(nb_cap + m_max + a.c.exact_q);
       asm volatile("" : "+s"(stride));
       const float inv_stride = 1.0f / static_cast<float>(stride);
       F = min(min(kFMax, W::elems / stride), it.i1 - g0);
       if (tid < F) {
         double f;
         int32_t nb;
-        grid_point(d, g0 + tid, noverlap, f, nb);
+        grid_point(d, g0 + tid, a.c, f, nb);
         g->f[tid] = f;
         g->nb[tid] = nb;
         g->blast[tid] = fold_bin_nc(dt_last, f, static_cast<double>(nb));
@@ -1193,7 +1193,7 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search_wide(SearchArgs a)
     const StarDesc d = a.stars[it.star];
     double f0;
     int32_t nb0;
-    grid_point(d, it.i0, a.c.noverlap, f0, nb0);
+    grid_point(d, it.i0, a.c, f0, nb0);
     if (nb0 <= kNbLimitBig || nb0 > kNbWide) continue;
     const StarRt rt = a.rt[it.star];
     const double w_unit = PACKED ? packed_w_unit(rt) : 0.0;
@@ -1208,7 +1208,7 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search_wide(SearchArgs a)
     for (int fi = it.i0; fi < it.i1; ++fi) {
       double f;
       int32_t nb;
-      grid_point(d, fi, a.c.noverlap, f, nb);
+      grid_point(d, fi, a.c, f, nb);
       if (nb <= kNbLimitBig) break;
       wide_frequency<PACKED>(smem, g, a, d, rt, fi, w_unit, dt, cw, cs, nchunks, run, chunk_pts, dt_last);
     }
@@ -1314,6 +1314,7 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
   a.c = plan->consts;
   const int64_t n_items = d_windows ? n_windows : static_cast<int64_t>(plan->items.size());
   if (n_items == 0) return BLS_OK;
+  if (plan->consts.rebin) return rebin_search(plan, base, d_windows, n_items, d_sr, d_best, st);
   a.n_items = static_cast<int32_t>(n_items);
   a.n_stars = plan->n_stars;
   int dev = 0, cus = 0;

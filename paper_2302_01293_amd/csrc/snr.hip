@@ -28,12 +28,22 @@ namespace mi355bls {
 
 namespace {
 
-__device__ __forceinline__ void grid_point_s(const StarDesc& d, int64_t i, int32_t noverlap, double& f,
-                                             int32_t& nb) {
+// Frequency i of a star's grid and the window geometry of its best-window record:
+// the fine-bin count and the window length for bls_best.m (with the per-duration
+// rebinning, m holds the duration index k: noverlap bins of the k-th set).
+__device__ __forceinline__ void window_geometry(const StarDesc& d, int64_t i, const Consts& c, int32_t m_rec,
+                                                double& f, int32_t& nb, int32_t& m) {
   const double u = d.umin + static_cast<double>(i) * d.A;
   const double uu = u * u;
   f = uu * u;
-  nb = static_cast<int32_t>(ceil(static_cast<double>(noverlap) / (d.kq * uu)));
+  if (c.rebin) {
+    const int32_t k = m_rec < 0 ? 0 : (m_rec >= c.n_rebin ? c.n_rebin - 1 : m_rec);
+    nb = rebin_bins(qlo_at(d, c, uu), c.rebin_g[k], c.noverlap);
+    m = c.noverlap;
+  } else {
+    nb = fine_bins(d, c, uu);
+    m = m_rec;
+  }
 }
 
 __device__ __forceinline__ double freq_s(const StarDesc& d, int64_t i) {
@@ -124,11 +134,12 @@ __device__ double residual_sigma(const StarDesc& d, const double* __restrict__ s
 // Summary of the chosen frequency i of a star (period, T0, duration, depth).
 __device__ bls_result make_result(const StarDesc& d, const double* sr, const bls_best* best_all, const TrendLds& L,
                                   int64_t i, int64_t i_sr, double snr, double sigma, int status, int nbins,
-                                  int32_t noverlap) {
+                                  const Consts& c) {
   bls_result r;
   double f;
   int32_t nb;
-  grid_point_s(d, i, noverlap, f, nb);
+  int32_t m;
+  window_geometry(d, i, c, best_all ? best_all[d.f_off + i].m : 0, f, nb, m);
   r.i_snr = i;
   r.i_sr = i_sr;
   r.period = 1.0 / f;
@@ -142,10 +153,10 @@ __device__ bls_result make_result(const StarDesc& d, const double* sr, const bls
   if (best_all) {
     const bls_best b = best_all[d.f_off + i];
     if (b.j >= 0) {
-      double ph = (static_cast<double>(b.j) + 0.5 * static_cast<double>(b.m)) / static_cast<double>(nb);
+      double ph = (static_cast<double>(b.j) + 0.5 * static_cast<double>(m)) / static_cast<double>(nb);
       ph = ph - floor(ph);
       r.t0 = d.t0 + ph / f;
-      r.duration = (static_cast<double>(b.m) / static_cast<double>(nb)) / f;
+      r.duration = (static_cast<double>(m) / static_cast<double>(nb)) / f;
       r.depth = -b.s / (b.r * (1.0 - b.r));
     }
   }
@@ -172,7 +183,7 @@ __device__ void snr_full(const StarDesc& d, const double* __restrict__ sr_all, c
   }
   bs = block_argmax(bs, L.red);
   bsr = block_argmax(bsr, L.red);
-  if (tid == 0) *out = make_result(d, sr, best_all, L, bs.i, bsr.i, bs.v, sigma, status, d.sturges, c.noverlap);
+  if (tid == 0) *out = make_result(d, sr, best_all, L, bs.i, bsr.i, bs.v, sigma, status, d.sturges, c);
 }
 
 template <int NT>
@@ -224,11 +235,11 @@ __global__ void __launch_bounds__(NT) k_snr_windows(
   bsr = block_argmax(bsr, L.red);
   if (tid == 0) {
     if (bs.i < 0) {  // no window frequency: nothing searched
-      bls_result r = make_result(d, sr, nullptr, L, 0, 0, 0.0, sigma, 2, dc.sturges, c.noverlap);
+      bls_result r = make_result(d, sr, nullptr, L, 0, 0, 0.0, sigma, 2, dc.sturges, c);
       r.sr = 0.0;
       res_all[s] = r;
     } else {
-      res_all[s] = make_result(d, sr, best_all, L, bs.i, bsr.i, bs.v, sigma, status, dc.sturges, c.noverlap);
+      res_all[s] = make_result(d, sr, best_all, L, bs.i, bsr.i, bs.v, sigma, status, dc.sturges, c);
     }
   }
 }

@@ -83,8 +83,14 @@ __global__ void __launch_bounds__(kStatThreads) k_stats(const StarDesc* __restri
       const double u = d.umin + static_cast<double>(r.i_snr) * d.A;
       const double uu = u * u;
       L.f = uu * u;
-      L.nb = static_cast<int32_t>(ceil(static_cast<double>(c.noverlap) / (d.kq * uu)));
-      L.m = bb.m;
+      if (c.rebin) {  // m holds the duration index k: noverlap bins of the k-th set
+        const bool kok = bb.m >= 0 && bb.m < c.n_rebin;
+        L.nb = kok ? rebin_bins(qlo_at(d, c, uu), c.rebin_g[bb.m], c.noverlap) : 1;
+        L.m = kok ? c.noverlap : 0;
+      } else {
+        L.nb = fine_bins(d, c, uu);
+        L.m = bb.m;
+      }
       L.j = bb.j;
       L.ok = (bb.m >= 1 && bb.m < L.nb && bb.j >= 0 && bb.j < L.nb) ? 1 : 0;
     }

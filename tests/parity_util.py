@@ -52,8 +52,10 @@ def _check_argmax(label, what, i_gpu, i_orc, spec_orc):
         label, what, i_gpu, i_orc, a, b)
 
 
-def compare_star(ds, orc, s_gpu, s_orc, batch_star, label=""):
-    """Compare one star's spectrum and summary; returns stats dict."""
+def compare_star(ds, orc, s_gpu, s_orc, batch_star, label="", geom=None):
+    """Compare one star's spectrum and summary; returns stats dict.  ``geom(f, m)``
+    maps a best-window record to (bins, window length) where that is not (the
+    oracle's nb, m), e.g. for the per-duration rebinning (m holds the duration index)."""
     sl = ds.star_slice(s_gpu)
     o0, o1 = int(orc["fofs"][s_orc]), int(orc["fofs"][s_orc + 1])
     sr_g = ds._sr_host[sl]
@@ -73,8 +75,12 @@ def compare_star(ds, orc, s_gpu, s_orc, batch_star, label=""):
         for i in mm:
             f, nb = orc["f"][o0 + i], orc["nb"][o0 + i]
             t0 = t[np.nonzero(w > 0)[0][0]]
-            pg = window_power(t, y, w, t0, f, nb, bg["m"][i], bg["j"][i])
-            po = window_power(t, y, w, t0, f, nb, orc["m"][o0 + i], orc["j"][o0 + i])
+            if geom is None:
+                (nbg, mg), (nbo, mo) = (nb, bg["m"][i]), (nb, orc["m"][o0 + i])
+            else:
+                (nbg, mg), (nbo, mo) = geom(f, bg["m"][i]), (nb, geom(f, orc["m"][o0 + i])[1])
+            pg = window_power(t, y, w, t0, f, nbg, mg, bg["j"][i]) if bg["j"][i] >= 0 else -1.0
+            po = window_power(t, y, w, t0, f, nbo, mo, orc["j"][o0 + i]) if orc["j"][o0 + i] >= 0 else -1.0
             assert abs(pg - po) <= NEAR_TIE_RTOL * max(abs(po), 1e-300), \
                 "%s: window differs at %d: gpu (%d,%d) %.17g vs oracle (%d,%d) %.17g" % (
                     label, i, bg["m"][i], bg["j"][i], pg, orc["m"][o0 + i], orc["j"][o0 + i], po)

@@ -186,3 +186,31 @@ def test_noalloc_rejects_plan_larger_than_scratch():
         pl.run_noalloc(1, 1, None, 1, None, None, 1)
     assert e.value.code == -8
     assert _lib.lib().bls_status_string(-8).startswith(b"workspace larger")
+
+
+@pytest.mark.parametrize("which", ["cfg0", "ragged"])
+def test_exact_duration_bins_identical_to_oracle(oracle, which):
+    # the host evaluates the exact duty cycle with the same libm asin as the oracle
+    b = synth.config0() if which == "cfg0" else synth.ragged(6, start=3)
+    plan = _plan_for(b, exact_duration=1)
+    small = _plan_for(b)
+    for s in range(b.n_stars):
+        t, y, w = b.star(s)
+        f_o, nb_o, _ = oracle.grid(t, w, float(b.rho[s]), oracle.params(exact_duration=1),
+                                   float(b.pmin[s]), float(b.pmax[s]))
+        f_p, nb_p = plan.frequencies(s)
+        assert np.array_equal(f_p.view(np.uint64), f_o.view(np.uint64))
+        assert np.array_equal(nb_p, nb_o)
+        assert np.all(nb_p <= small.frequencies(s)[1])
+
+
+def test_variant_parameters_checked():
+    b = synth.ragged(2, start=0)
+    for bad in (dict(rebin=1, precision=1), dict(rebin=1, dlogq=0.01)):   # packed sums; > 32 durations
+        with pytest.raises(_lib.BlsError) as e:
+            _plan_for(b, **bad)
+        assert e.value.code == -7
+    for bad in (dict(rebin=2), dict(exact_duration=-1)):
+        with pytest.raises(_lib.BlsError) as e:
+            _plan_for(b, **bad)
+        assert e.value.code == -1
