@@ -12,9 +12,13 @@ Three run-time choices of the plan change only speed, never results:
     one (48 KB, three per CU): fewer point re-reads per frequency against less
     latency hiding.
 The best values depend on the device and on the batch shape, so they are measured:
-coordinate descent over the three axes, each candidate timed on a stratified sample
-of the batch's stars (device time of ``bls_search_batch``, median of a few
-launches), the winners cached per device and batch shape in a JSON file.
+coordinate descent over the three axes, each candidate timed on the batch or a
+stratified sample of its stars (device time of ``bls_search_batch``, median of a few
+launches), the winners cached per device and batch shape in a JSON file.  Each axis
+also times the current pick (the library default at first), so the result is never
+slower than the default on what was timed; a small sample can still mislead (a few
+dozen stars do not fill 256 CUs the way a full batch does), so callers that care
+time the batch itself.
 """
 from __future__ import annotations
 
@@ -69,12 +73,13 @@ def sample_stars(points: np.ndarray, n: int, seed: int = 0) -> np.ndarray:
     return np.unique(picks)
 
 
-def _time_search(sub, params, reps: int) -> float:
+def _time_search(sub, params, reps: int, warmup: bool = True) -> float:
     import torch
     from .device import DeviceSearch
     ds = DeviceSearch.from_batch(sub, params, want_snr=False, want_best=False)
     ds.run_prepare()
-    ds.run_search()  # warm-up
+    if warmup:
+        ds.run_search()
     stream = torch.cuda.current_stream()
     ms = []
     for _ in range(reps):
@@ -90,11 +95,14 @@ def _time_search(sub, params, reps: int) -> float:
 
 def tune(batch, params=None, candidates=CANDIDATES, n_sample: int = 256, reps: int = 3,
          cache_path: str | None = None, use_cache: bool = True, axes=("tile_cells",),
-         item_freqs=ITEM_FREQS, big_points=BIG_POINTS, log=None) -> dict:
+         item_freqs=ITEM_FREQS, big_points=BIG_POINTS, log=None, include_current: bool = True,
+         warmup: bool = True) -> dict:
     """Pick the schedule for a batch by coordinate descent over ``axes`` (any of
     "tile_cells", "item_freqs", "big_points", tuned in that order, each with the
-    others at their current picks); returns {"tile_cells", "item_freqs",
-    "big_points", "times_ms", "key", "cached"} (0 = library default)."""
+    others at their current picks; with ``include_current`` the current pick is one
+    of each axis's candidates, a schedule is timed once); returns {"tile_cells",
+    "item_freqs", "big_points", "times_ms", "key", "cached", and when timed here
+    "default_ms" and "best_ms"} (0 = library default)."""
     import torch
     from . import _lib
 
@@ -112,21 +120,31 @@ def tune(batch, params=None, candidates=CANDIDATES, n_sample: int = 256, reps: i
     pick = dict(tile_cells=int(base.tile_cells), item_freqs=int(base.item_freqs), big_points=int(base.big_points))
     grid = dict(tile_cells=candidates, item_freqs=item_freqs, big_points=big_points)
     times = {}
+    seen = {}
     for ax in ("tile_cells", "item_freqs", "big_points"):
         if ax not in axes:
             continue
+        cands = [int(c) for c in grid[ax]]
+        if include_current and pick[ax] not in cands:
+            cands = [pick[ax]] + cands
         res = {}
-        for c in grid[ax]:
-            p = _lib.default_params(**{f: getattr(base, f) for f, _ in _lib.BlsParams._fields_})
-            for k, v in pick.items():
-                setattr(p, k, int(v))
-            setattr(p, ax, int(c))
-            res[str(c)] = _time_search(sub, p, reps)
+        for c in cands:
+            sched = dict(pick, **{ax: c})
+            tag = (sched["tile_cells"], sched["item_freqs"], sched["big_points"])
+            if tag not in seen:
+                p = _lib.default_params(**{f: getattr(base, f) for f, _ in _lib.BlsParams._fields_})
+                for k, v in sched.items():
+                    setattr(p, k, int(v))
+                seen[tag] = _time_search(sub, p, reps, warmup)
+            res[str(c)] = seen[tag]
             if log:
                 log("autotune %s = %d: %.2f ms" % (ax, c, res[str(c)]))
         pick[ax] = int(min(res, key=lambda k: res[k]))
         times[ax] = res
-    out = dict(pick, times_ms=times, key=key, cached=False)
+    base_tag = (int(base.tile_cells), int(base.item_freqs), int(base.big_points))
+    best_tag = (pick["tile_cells"], pick["item_freqs"], pick["big_points"])
+    out = dict(pick, times_ms=times, key=key, cached=False, default_ms=seen.get(base_tag),
+               best_ms=seen.get(best_tag))
     if use_cache:
         cache[key] = dict(pick, times_ms=times)
         save_cache(path, cache)

@@ -51,8 +51,10 @@ def run_stream(batches, params=None, log=None, autotune_first: bool = False):
         if bi == 0 and autotune_first:
             from . import autotune
             base = params if params is not None else _lib.default_params()
-            schedule = autotune.tune(b, base, n_sample=48, reps=2, use_cache=False,
-                                     axes=("tile_cells", "item_freqs", "big_points"))
+            schedule = autotune.tune(b, base, n_sample=b.n_stars, reps=1, use_cache=False,
+                                     axes=("tile_cells", "item_freqs", "big_points"),
+                                     candidates=(3 << 20, 12 << 20), item_freqs=(64, 256),
+                                     big_points=(50_000, 200_000), warmup=False)
             params = _lib.default_params(**{f: getattr(base, f) for f, _ in _lib.BlsParams._fields_})
             for k in ("tile_cells", "item_freqs", "big_points"):
                 setattr(params, k, int(schedule[k]))
