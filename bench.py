@@ -151,11 +151,14 @@ def make_workload(name: str, n_stars: int, batch_stars: int, steps: int):
     raise SystemExit("unknown workload %s" % name)
 
 
-def cpu_baseline_cells(batches, stride: int, cells_per_star: float):
+def cpu_baseline_cells(batches, stride: int, cells_per_star: float, params=None):
     """The oracle as it stands on a bounded sample of the benchmark's stars: one star
     per sector count (stratified), every ``stride``-th frequency of its grid (each
     frequency searched in full: fold, bins, every window).  Throughput in cells/s
-    is extrapolated to stars/hour with the workload's mean cells per star."""
+    is extrapolated to stars/hour with the workload's mean cells per star.  The same
+    stars are then searched on the GPU with the benchmark's parameters and the SR at
+    those frequencies compared with the oracle's (relative error per result, and the
+    share of equal best windows)."""
     from concurrent.futures import ThreadPoolExecutor
 
     from oracle import oracle
@@ -177,22 +180,48 @@ def cpu_baseline_cells(batches, stride: int, cells_per_star: float):
 
     def run(j):
         t, y, w, rho, idx, _ = j
-        oracle.bls_star_at(t, y, w, idx, rho)
+        return oracle.bls_star_at(t, y, w, idx, rho)
 
     oracle.lib()
+    order = sorted(range(len(jobs)), key=lambda i: -jobs[i][5])
     t0 = time.perf_counter()
     with ThreadPoolExecutor(cores) as ex:
-        list(ex.map(run, sorted(jobs, key=lambda j: -j[5])))
+        specs = list(ex.map(run, [jobs[i] for i in order]))
     dt = time.perf_counter() - t0
+    spec_of = {i: sp for i, sp in zip(order, specs)}
     cells = float(sum(j[5] for j in jobs))
     cps = cells / dt
+    sr_err = None
+    if params is not None:
+        import torch
+        from paper_2302_01293_amd import synth
+        from paper_2302_01293_amd.device import DeviceSearch
+        sub = synth.concat([batches[bi].subset([s]) for bi, s in picks])
+        ds = DeviceSearch.from_batch(sub, params, want_snr=False)
+        ds.run()
+        torch.cuda.synchronize()
+        sr_g, best_g = ds.sr_host(), ds.best_host()
+        rels, same, tot = [], 0, 0
+        for i, (t, y, w, rho, idx, _) in enumerate(jobs):
+            f0 = int(ds.plan.freq_offsets[i])
+            o = spec_of[i]
+            g = sr_g[f0 + idx]
+            rels.append(np.abs(g - o.sr) / np.maximum(np.abs(o.sr), 1e-300))
+            bg = best_g[f0 + idx]
+            same += int(np.sum((bg["m"] == o.m) & (bg["j"] == o.j)))
+            tot += len(idx)
+        rel = np.concatenate(rels)
+        sr_err = dict(results=int(tot), stars=len(jobs), max_rel=float(rel.max()),
+                      p99_rel=float(np.percentile(rel, 99)), median_rel=float(np.median(rel)),
+                      best_window_equal=same / tot)
+        del ds
     return dict(value=cps / cells_per_star * 3600.0, unit="stars/hour", cores=cores, kind="oracle",
                 sample=("%d stars of the workload (one per sector count %d-%d), 1 in %d grid frequencies "
                         "of each: %.3g cells in %.1f s = %.3g cells/s, extrapolated with the workload's "
                         "%.3g cells per star (the S/N step, O(N_f log N_f), is not timed)"
                         % (len(jobs), min(seen), max(seen), stride, cells, dt, cps, cells_per_star)),
                 cells_per_s=cps, nproc=os.cpu_count(), cpu_model=cpu_model(),
-                single_core_s_per_star=cells_per_star / (cps / cores))
+                single_core_s_per_star=cells_per_star / (cps / cores), sr_vs_oracle=sr_err)
 
 
 def cpu_baseline_full(batch, n_sample: int, seed: int = 7):
@@ -459,6 +488,20 @@ def main():
                      "kernel": "k_search (fold + boundary accumulation + scan; all launches of "
                                "bls_search_batch)"},
     }
+    # HBM fractions of the two streaming kernels of the step (algorithmic bytes: the
+    # preparation reads t, y, w and writes dt and the two prefix sums, 48 B per point;
+    # the S/N step reads SR once, 8 B per frequency, and writes 88 B per star); the
+    # preparation interval also holds the plan's descriptor upload
+    pts_step = float(np.mean([steps[k % n_batches].batch.n_points for k in range(args.steps)]))
+    nf_step = float(np.mean([sizes[k % n_batches]["nf"] for k in range(args.steps)]))
+    st_step = float(np.mean([steps[k % n_batches].batch.n_stars for k in range(args.steps)]))
+    other = {}
+    for name, by, ms in (("k_prepare", 48.0 * pts_step, float(prep.mean())),
+                         ("k_snr", 8.0 * nf_step + 88.0 * st_step, float(snr.mean()))):
+        gbs = by / (ms * 1e-3) / 1e9
+        other[name] = {"bound": "hbm", "bytes_per_step": by, "ms": ms, "achieved": gbs, "peak": 8000.0,
+                       "unit": "GB/s", "frac": gbs / 8000.0}
+    out["other_kernels"] = other
     if not args.no_ceilings:
         c = measure_ceilings()
         out["ceilings"] = c
@@ -475,7 +518,11 @@ def main():
         log("cpu baseline (oracle) on a sample ...")
         if args.workload == "cfg4":
             out["cpu_baseline"] = cpu_baseline_cells([s.batch for s in steps], args.cpu_stride,
-                                                     cells / n_timed)
+                                                     cells / n_timed, params)
+            e = out["cpu_baseline"]["sr_vs_oracle"]
+            log("GPU SR against the oracle at the sampled frequencies: max %.2e, p99 %.2e, median %.2e relative "
+                "over %d results; best windows equal for %.6f" % (e["max_rel"], e["p99_rel"], e["median_rel"],
+                                                                   e["results"], e["best_window_equal"]))
         else:
             out["cpu_baseline"] = cpu_baseline_full(batches[0], args.cpu_sample)
         log("cpu baseline: %.4g stars/hour" % out["cpu_baseline"]["value"])
