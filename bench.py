@@ -507,6 +507,15 @@ def main():
         out["ceilings"] = c
         out["roofline"]["measured_peak"] = c["fp64_ops_per_s"] / 1e12
         out["roofline"]["frac_of_measured"] = achieved / (c["fp64_ops_per_s"] / 1e12)
+        # The fold's other bound: each wave-step (64 points at one frequency) adds the
+        # boundary's two int64 prefix values to LDS with two ds_add_u64 whenever any
+        # of its lanes enters a new bin, which on these grids is every step (3-25
+        # points per bin visit); at the measured cycles per such instruction the
+        # LDS caps the search at this many cells/s.
+        cyc = c["lds_add_u64_cu_cycles_64_lanes"]
+        lds_cap = 256 * c["clock_GHz"] * 1e9 / (2.0 * cyc) * 64.0
+        out["roofline"]["lds_atomic_bound"] = {"cells_per_s": lds_cap, "frac": (cells / search_s) / lds_cap,
+                                               "basis": "2 ds_add_u64 per 64-cell wave-step at %.2f CU-cycles" % cyc}
         log("ceilings: DMUL %.2f FRACT %.2f SIMD-cycles per wave instruction; 64-bit LDS atomic %.2f CU-cycles; "
             "copy %.0f GB/s" % (c["dmul_simd_cycles"], c["fract_simd_cycles"], c["lds_add_u64_cu_cycles_64_lanes"],
                                 c["hbm_copy_GBps"]))

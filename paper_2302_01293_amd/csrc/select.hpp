@@ -26,6 +26,7 @@ __device__ __forceinline__ double value_of(unsigned long long k) {
 }
 
 constexpr int kSelBuckets = 2048;  // histogram buckets per pass (11 bits of key range)
+constexpr int kSelUnroll = 4;      // values loaded per thread before any is used (loads in flight)
 constexpr int kSelCap = 1024;      // candidates finished in LDS
 
 struct SelShared {
@@ -71,15 +72,40 @@ __device__ __forceinline__ void find_bucket(int nb, long long r, SelShared& sh) 
   __syncthreads();
 }
 
+// Keys of v(base + u T + tid), u < kSelUnroll, for the indices below hi (ok[u]); all
+// loads are issued before the first key is formed, so a pass waits on its loads once
+// per kSelUnroll values instead of once per value.
+template <typename F>
+__device__ __forceinline__ void load_keys(F v, int64_t base, int64_t hi, unsigned long long (&k)[kSelUnroll],
+                                          bool (&ok)[kSelUnroll]) {
+  const int64_t T = blockDim.x, tid = threadIdx.x;
+  double x[kSelUnroll];
+#pragma unroll
+  for (int u = 0; u < kSelUnroll; ++u) {
+    const int64_t i = base + u * T + tid;
+    ok[u] = i < hi;
+    x[u] = ok[u] ? v(i) : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kSelUnroll; ++u) k[u] = key_of(x[u]);
+}
+
 // Block-wide minimum and maximum of the keys of v(i), i in [lo, hi).
 template <typename F>
 __device__ void block_key_range(F v, int64_t lo, int64_t hi, SelShared& sh) {
   const int tid = threadIdx.x, T = blockDim.x, lane = tid & 63, wave = tid >> 6;
   unsigned long long mn = ~0ull, mx = 0ull;
-  for (int64_t i = lo + tid; i < hi; i += T) {
-    const unsigned long long k = key_of(v(i));
-    mn = k < mn ? k : mn;
-    mx = k > mx ? k : mx;
+  for (int64_t b0 = lo; b0 < hi; b0 += static_cast<int64_t>(kSelUnroll) * T) {
+    unsigned long long k[kSelUnroll];
+    bool ok[kSelUnroll];
+    load_keys(v, b0, hi, k, ok);
+#pragma unroll
+    for (int u = 0; u < kSelUnroll; ++u) {
+      if (ok[u]) {
+        mn = k[u] < mn ? k[u] : mn;
+        mx = k[u] > mx ? k[u] : mx;
+      }
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -136,24 +162,25 @@ __device__ void block_select_keys(F v, int64_t lo, int64_t hi, int64_t rank, boo
     const int nb = static_cast<int>(span >> shift) + 1;
     for (int q = tid; q < nb; q += T) sh.hist[q] = 0;
     __syncthreads();
-    for (int64_t i0 = lo; i0 < hi; i0 += T) {
-      const int64_t i = i0 + tid;
-      bool take = false;
-      int bk = 0;
-      if (i < hi) {
-        const unsigned long long k = key_of(v(i));
-        take = k >= base && k - base <= span;
-        bk = take ? static_cast<int>((k - base) >> shift) : 0;
-      }
-      // a wave whose keys share one bucket adds its count once
-      const unsigned long long m = __ballot(take);
-      if (m) {
-        const int leader = __ffsll(static_cast<long long>(m)) - 1;
-        const int lb = __shfl(bk, leader, 64);
-        if (__ballot(take && bk == lb) == m) {
-          if (lane == leader) atomicAdd(&sh.hist[lb], static_cast<unsigned>(__popcll(m)));
-        } else if (take) {
-          atomicAdd(&sh.hist[bk], 1u);
+    for (int64_t b0 = lo; b0 < hi; b0 += static_cast<int64_t>(kSelUnroll) * T) {
+      unsigned long long kk[kSelUnroll];
+      bool ok[kSelUnroll];
+      load_keys(v, b0, hi, kk, ok);
+#pragma unroll
+      for (int u = 0; u < kSelUnroll; ++u) {
+        const unsigned long long k = kk[u];
+        const bool take = ok[u] && k >= base && k - base <= span;
+        const int bk = take ? static_cast<int>((k - base) >> shift) : 0;
+        // a wave whose keys share one bucket adds its count once
+        const unsigned long long m = __ballot(take);
+        if (m) {
+          const int leader = __ffsll(static_cast<long long>(m)) - 1;
+          const int lb = __shfl(bk, leader, 64);
+          if (__ballot(take && bk == lb) == m) {
+            if (lane == leader) atomicAdd(&sh.hist[lb], static_cast<unsigned>(__popcll(m)));
+          } else if (take) {
+            atomicAdd(&sh.hist[bk], 1u);
+          }
         }
       }
     }
@@ -180,9 +207,13 @@ __device__ void block_select_keys(F v, int64_t lo, int64_t hi, int64_t rank, boo
             out_b = blo;
           } else {  // the next key above this bucket
             unsigned long long mnx = ~0ull;
-            for (int64_t i = lo + tid; i < hi; i += T) {
-              const unsigned long long k = key_of(v(i));
-              if (k > blo && k < mnx) mnx = k;
+            for (int64_t b0 = lo; b0 < hi; b0 += static_cast<int64_t>(kSelUnroll) * T) {
+              unsigned long long kk[kSelUnroll];
+              bool ok[kSelUnroll];
+              load_keys(v, b0, hi, kk, ok);
+#pragma unroll
+              for (int u = 0; u < kSelUnroll; ++u)
+                if (ok[u] && kk[u] > blo && kk[u] < mnx) mnx = kk[u];
             }
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) {
@@ -204,11 +235,16 @@ __device__ void block_select_keys(F v, int64_t lo, int64_t hi, int64_t rank, boo
         return;
       }
       // gather the bucket's keys into LDS
-      for (int64_t i = lo + tid; i < hi; i += T) {
-        const unsigned long long k = key_of(v(i));
-        if (k >= blo && k - blo <= bspan) {
-          const unsigned int slot = atomicAdd(&sh.ncand, 1u);
-          sh.cand[slot] = k;
+      for (int64_t b0 = lo; b0 < hi; b0 += static_cast<int64_t>(kSelUnroll) * T) {
+        unsigned long long kk[kSelUnroll];
+        bool ok[kSelUnroll];
+        load_keys(v, b0, hi, kk, ok);
+#pragma unroll
+        for (int u = 0; u < kSelUnroll; ++u) {
+          if (ok[u] && kk[u] >= blo && kk[u] - blo <= bspan) {
+            const unsigned int slot = atomicAdd(&sh.ncand, 1u);
+            sh.cand[slot] = kk[u];
+          }
         }
       }
       __syncthreads();
@@ -232,9 +268,13 @@ __device__ void block_select_keys(F v, int64_t lo, int64_t hi, int64_t rank, boo
         } else {  // the next key above this bucket
           unsigned long long mnx = ~0ull;
           const unsigned long long top = blo + bspan;
-          for (int64_t i = lo + tid; i < hi; i += T) {
-            const unsigned long long k = key_of(v(i));
-            if (k > top && k < mnx) mnx = k;
+          for (int64_t b0 = lo; b0 < hi; b0 += static_cast<int64_t>(kSelUnroll) * T) {
+            unsigned long long kk[kSelUnroll];
+            bool ok[kSelUnroll];
+            load_keys(v, b0, hi, kk, ok);
+#pragma unroll
+            for (int u = 0; u < kSelUnroll; ++u)
+              if (ok[u] && kk[u] > top && kk[u] < mnx) mnx = kk[u];
           }
 #pragma unroll
           for (int o = 32; o > 0; o >>= 1) {
