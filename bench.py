@@ -270,7 +270,7 @@ def main():
                     help="skip the learned-proposal comparison (trained weights vs the plain path)")
     ap.add_argument("--learned-batches", type=int, default=8,
                     help="cfg4: steps' batches on which the learned path is compared with the plain one")
-    ap.add_argument("--learned-points", default="0.5:8:4,0.9:8:0,0:0:4,0:0:2,0:8:2",
+    ap.add_argument("--learned-points", default="0.9:8:4,0.5:8:4,0.9:8:0,0:0:4,0:0:2,0:8:2",
                     help="operating points of the learned path, conf:topk:coarse_peaks (coarse_peaks > 0: "
                          "windows guided by that many peaks of the coarse S/N spectrum, no blanket window "
                          "beyond 100 d; topk 0: no network windows); the first is the headline")
