@@ -630,6 +630,31 @@ def learned_vs_plain(args, steps, plain_results, plain_ms, params):
                                conf_stats["confident_recovered"], conf_stats["confident_detections"], pt["speedup"],
                                pt["fallback_fraction"]))
         out["points"].append(pt)
+    # The network's forward pass on the first batch's resampled light curves: the
+    # two convolutions are the MFMA work, 2*2048*16*(2*16) + 2*1024*16*(16*8) =
+    # 6.29 MFLOP per light curve on BF16 inputs (the autocorrelation and head, FP32
+    # and FP64, are in the same launch and not counted).
+    b0 = steps[0].batch
+    ls = learned.LearnedSearch(b0, net, params=params)
+    ls.fine.run_prepare()
+    x, lag = learned.resample(ls.fine)
+    net.forward(x, lag)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record(stream)
+    for _ in range(reps):
+        net.forward(x, lag)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / reps
+    flops = 6.291456e6 * b0.n_stars
+    out["k_forward"] = {"light_curves": b0.n_stars, "ms": fwd_ms, "mfma_flops": flops, "bound": "mfma",
+                        "achieved": flops / (fwd_ms * 1e-3) / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                        "frac": flops / (fwd_ms * 1e-3) / 1e12 / 2500.0}
+    log("network forward on %d light curves: %.3f ms, %.2f TFLOP/s of BF16 MFMA work (%.2e of peak)"
+        % (b0.n_stars, fwd_ms, out["k_forward"]["achieved"], out["k_forward"]["frac"]))
+    del ls
     h = out["points"][0]
     out["headline"] = dict(kind=h["kind"], conf=h["conf"], topk=h["topk"], coarse_peaks=h["coarse_peaks"],
                            recovery=h["recovery"], speedup=h["speedup"],

@@ -38,11 +38,17 @@
 
 namespace mi355bls {
 
+// EXQ: the exact circular duration (its arcsine only in the kernels that need it,
+// so that the others' register allocation does not carry it).
+template <bool EXQ>
 __device__ __forceinline__ void grid_point(const StarDesc& d, int64_t i, const Consts& c, double& f, int32_t& nb) {
   const double u = d.umin + static_cast<double>(i) * d.A;
   const double uu = u * u;
   f = uu * u;
-  nb = fine_bins(d, c, uu);
+  if constexpr (EXQ)
+    nb = fine_bins(d, c, uu);
+  else
+    nb = static_cast<int32_t>(ceil(static_cast<double>(c.noverlap) / (d.kq * uu)));
 }
 
 // Fine bin of a point: b = min(nb-1, floor(frac(dt f) nb)).
@@ -561,7 +567,7 @@ __device__ bool next_item(const SearchArgs& a, GroupLds* g, int& queue, int& pro
       if (tid < 64) {
         double f;
         int32_t nb;
-        grid_point(d, it.i1 - 1, a.c, f, nb);
+        grid_point<false>(d, it.i1 - 1, a.c, f, nb);  // f only
         const double thr = 0.99 / (static_cast<double>(a.c.noverlap) * cbrt(f) / d.kq + f);
         const int c = count_at_least(a.gap_steps + d.g_off, d.n_gaps, thr);
         if (tid == 0) g->item[1] = c;
@@ -630,7 +636,7 @@ __device__ __forceinline__ void fold_wide(unsigned char* smem, double f, double 
   }
 }
 
-template <bool PACKED>
+template <bool PACKED, bool EXQ>
 __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArgs& a, const StarDesc& d,
                                const StarRt& rt, int fi, double w_unit, const double* __restrict__ dt,
                                const int64_t* __restrict__ cw, const int64_t* __restrict__ cs, int nchunks, int run,
@@ -646,7 +652,7 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
   const int64_t n = d.n;
   double f;
   int32_t nb;
-  grid_point(d, fi, a.c, f, nb);
+  grid_point<EXQ>(d, fi, a.c, f, nb);
   const double nbd = static_cast<double>(nb);
   const int32_t blast = fold_bin_nc(dt_last, f, nbd);
   const int mlim = min(m_max, nb - 1);
@@ -843,7 +849,7 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
 // DIP: only windows with s < 0 (dips) count.  BIG: the large workgroup shape, for
 // the frequencies whose fine-bin count lies in (kNbLimit, kNbLimitBig] and for every
 // frequency up to kNbLimitBig bins of stars with more than big_points points.
-template <bool PACKED, bool DFORM, bool DIP, bool BIG>
+template <bool PACKED, bool DFORM, bool DIP, bool BIG, bool EXQ>
 __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search(SearchArgs a) {
   using W = Win<BIG>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -882,7 +888,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
     {
       double f_first;
       int32_t nb_first;
-      grid_point(d, it.i0, a.c, f_first, nb_first);
+      grid_point<EXQ>(d, it.i0, a.c, f_first, nb_first);
       if (nb_first > kNbWide || nb_first < 1) continue;  // rejected by the plan
     }
 
@@ -919,7 +925,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
       // group lets long ranges take more frequencies per group as nb shrinks.
       double f_g;
       int32_t nb_cap;
-      grid_point(d, g0, a.c, f_g, nb_cap);
+      grid_point<EXQ>(d, g0, a.c, f_g, nb_cap);
       if (nb_cap > W::nb_hi) {  // searched by the large shape or k_search_wide
         F = 1;
         continue;
@@ -927,14 +933,14 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
       if (BIG && !long_star && nb_cap <= W::nb_lo) break;  // nb falls with frequency: the rest are the common shape's
       // with exact durations the count goes through the device asin, which need not
       // be monotone in its last place: one bin of room for a later frequency's count
-      int stride = __builtin_amdgcn_readfirstlane(nb_cap + m_max + a.c.exact_q);
+      int stride = __builtin_amdgcn_readfirstlane(nb_cap + m_max + (EXQ ? 1 : 0));
       asm volatile("" : "+s"(stride));
       const float inv_stride = 1.0f / static_cast<float>(stride);
       F = min(min(kFMax, W::elems / stride), it.i1 - g0);
       if (tid < F) {
         double f;
         int32_t nb;
-        grid_point(d, g0 + tid, a.c, f, nb);
+        grid_point<EXQ>(d, g0 + tid, a.c, f, nb);
         g->f[tid] = f;
         g->nb[tid] = nb;
         g->blast[tid] = fold_bin_nc(dt_last, f, static_cast<double>(nb));
@@ -1180,7 +1186,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
 // Frequencies with more fine bins than a large-shape group holds (kNbLimitBig);
 // k_search skips them.  Same work list; nb falls with frequency, so the wide frequencies of
 // an item are a prefix of its range.
-template <bool PACKED>
+template <bool PACKED, bool EXQ>
 __global__ void __launch_bounds__(kSearchThreads, 4) k_search_wide(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   GroupLds* g = reinterpret_cast<GroupLds*>(smem + Win<true>::bytes);
@@ -1193,7 +1199,7 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search_wide(SearchArgs a)
     const StarDesc d = a.stars[it.star];
     double f0;
     int32_t nb0;
-    grid_point(d, it.i0, a.c, f0, nb0);
+    grid_point<EXQ>(d, it.i0, a.c, f0, nb0);
     if (nb0 <= kNbLimitBig || nb0 > kNbWide) continue;
     const StarRt rt = a.rt[it.star];
     const double w_unit = PACKED ? packed_w_unit(rt) : 0.0;
@@ -1208,9 +1214,9 @@ __global__ void __launch_bounds__(kSearchThreads, 4) k_search_wide(SearchArgs a)
     for (int fi = it.i0; fi < it.i1; ++fi) {
       double f;
       int32_t nb;
-      grid_point(d, fi, a.c, f, nb);
+      grid_point<EXQ>(d, fi, a.c, f, nb);
       if (nb <= kNbLimitBig) break;
-      wide_frequency<PACKED>(smem, g, a, d, rt, fi, w_unit, dt, cw, cs, nchunks, run, chunk_pts, dt_last);
+      wide_frequency<PACKED, EXQ>(smem, g, a, d, rt, fi, w_unit, dt, cw, cs, nchunks, run, chunk_pts, dt_last);
     }
   }
 }
@@ -1262,31 +1268,41 @@ extern "C" bls_status bls_prepare(bls_plan* plan, void* ws, const double* d_t, c
   return BLS_OK;
 }
 
+template <bool BIG, bool EXQ>
+static void launch_search_x(bool packed, bool dform, bool dip, const dim3& gd, const dim3& bd, size_t lds,
+                            hipStream_t st, const SearchArgs& a) {
+  if (packed) {
+    if (dform) {
+      if (dip) hipLaunchKernelGGL((k_search<true, true, true, BIG, EXQ>), gd, bd, lds, st, a);
+      else hipLaunchKernelGGL((k_search<true, true, false, BIG, EXQ>), gd, bd, lds, st, a);
+    } else {
+      if (dip) hipLaunchKernelGGL((k_search<true, false, true, BIG, EXQ>), gd, bd, lds, st, a);
+      else hipLaunchKernelGGL((k_search<true, false, false, BIG, EXQ>), gd, bd, lds, st, a);
+    }
+  } else {
+    if (dform) {
+      if (dip) hipLaunchKernelGGL((k_search<false, true, true, BIG, EXQ>), gd, bd, lds, st, a);
+      else hipLaunchKernelGGL((k_search<false, true, false, BIG, EXQ>), gd, bd, lds, st, a);
+    } else {
+      if (dip) hipLaunchKernelGGL((k_search<false, false, true, BIG, EXQ>), gd, bd, lds, st, a);
+      else hipLaunchKernelGGL((k_search<false, false, false, BIG, EXQ>), gd, bd, lds, st, a);
+    }
+  }
+}
+
 // The instantiations of k_search for one workgroup shape (packed sums, difference
-// form, dips only), as a persistent grid of `groups` workgroups per CU.
+// form, dips only, exact durations), as a persistent grid of `groups` workgroups
+// per CU.
 template <bool BIG>
-static void launch_search(bool packed, bool dform, bool dip, int64_t n_items, int cus, hipStream_t st,
+static void launch_search(bool packed, bool dform, bool dip, bool exq, int64_t n_items, int cus, hipStream_t st,
                           const SearchArgs& a) {
   const int64_t grid = std::min<int64_t>(n_items, Win<BIG>::groups * static_cast<int64_t>(cus));
   const dim3 gd(static_cast<unsigned>(grid)), bd(kSearchThreads);
   const size_t lds = search_lds<BIG>();
-  if (packed) {
-    if (dform) {
-      if (dip) hipLaunchKernelGGL((k_search<true, true, true, BIG>), gd, bd, lds, st, a);
-      else hipLaunchKernelGGL((k_search<true, true, false, BIG>), gd, bd, lds, st, a);
-    } else {
-      if (dip) hipLaunchKernelGGL((k_search<true, false, true, BIG>), gd, bd, lds, st, a);
-      else hipLaunchKernelGGL((k_search<true, false, false, BIG>), gd, bd, lds, st, a);
-    }
-  } else {
-    if (dform) {
-      if (dip) hipLaunchKernelGGL((k_search<false, true, true, BIG>), gd, bd, lds, st, a);
-      else hipLaunchKernelGGL((k_search<false, true, false, BIG>), gd, bd, lds, st, a);
-    } else {
-      if (dip) hipLaunchKernelGGL((k_search<false, false, true, BIG>), gd, bd, lds, st, a);
-      else hipLaunchKernelGGL((k_search<false, false, false, BIG>), gd, bd, lds, st, a);
-    }
-  }
+  if (exq)
+    launch_search_x<BIG, true>(packed, dform, dip, gd, bd, lds, st, a);
+  else
+    launch_search_x<BIG, false>(packed, dform, dip, gd, bd, lds, st, a);
 }
 
 extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* d_windows, int64_t n_windows,
@@ -1325,16 +1341,16 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
   // shape, then (when the batch needs them) stars whose steps mostly skip fine bins
   // in difference form, the large shape for frequencies with more fine bins, and
   // the frequencies beyond one LDS pass.  Each launch skips the others' work.
-  const bool packed = plan->consts.packed != 0, dip = a.c.dip_only != 0;
+  const bool packed = plan->consts.packed != 0, dip = a.c.dip_only != 0, exq = a.c.exact_q != 0;
   const bool dform = d_windows ? plan->has_dform_star : plan->has_dform;
   for (int big = 0; big < (plan->has_big ? 2 : 1); ++big) {
     for (int df = 0; df < (dform ? 2 : 1); ++df) {
       hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);  // 8 counters
       BLS_HIP_TRY(hipGetLastError());
       if (big)
-        launch_search<true>(packed, df != 0, dip, n_items, cus, st, a);
+        launch_search<true>(packed, df != 0, dip, exq, n_items, cus, st, a);
       else
-        launch_search<false>(packed, df != 0, dip, n_items, cus, st, a);
+        launch_search<false>(packed, df != 0, dip, exq, n_items, cus, st, a);
       BLS_HIP_TRY(hipGetLastError());
     }
   }
@@ -1342,12 +1358,14 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);
     BLS_HIP_TRY(hipGetLastError());
     const int64_t grid = std::min<int64_t>(n_items, kSearchGroupsPerCuBig * static_cast<int64_t>(cus));
-    if (packed)
-      hipLaunchKernelGGL(k_search_wide<true>, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads),
-                         search_lds<true>(), st, a);
-    else
-      hipLaunchKernelGGL(k_search_wide<false>, dim3(static_cast<unsigned>(grid)), dim3(kSearchThreads),
-                         search_lds<true>(), st, a);
+    const dim3 gd(static_cast<unsigned>(grid)), bd(kSearchThreads);
+    if (packed) {
+      if (exq) hipLaunchKernelGGL((k_search_wide<true, true>), gd, bd, search_lds<true>(), st, a);
+      else hipLaunchKernelGGL((k_search_wide<true, false>), gd, bd, search_lds<true>(), st, a);
+    } else {
+      if (exq) hipLaunchKernelGGL((k_search_wide<false, true>), gd, bd, search_lds<true>(), st, a);
+      else hipLaunchKernelGGL((k_search_wide<false, false>), gd, bd, search_lds<true>(), st, a);
+    }
   }
   BLS_HIP_TRY(hipGetLastError());
   return BLS_OK;
