@@ -21,9 +21,14 @@
 // the BLS mid-time, depth and duration, q_in = 0.2, z = the weighted mean of the fit
 // points outside the starting box.
 //
-// One 256-thread workgroup per star.  The fit's sums (15 of A, 5 of g, chi^2) are
-// per-thread partial sums over a strided walk of the star's points, combined in a
-// fixed order, so results are deterministic; the noise and transit passes walk
+// One workgroup per star (256 or 512 threads, see below).  The times are sorted, so the points within two
+// starting durations of a mid-transit form one index range per transit epoch: the
+// ranges (found by binary search with a small margin; the exact test is still made
+// per point) are kept in LDS and the fit's passes walk only them, spread evenly over
+// the threads (stars with more epochs than LDS holds, or durations of a quarter
+// period or more, walk every point).  The fit's sums (15 of A, 5 of g, chi^2) are
+// per-thread partial sums over that walk, combined in a fixed order, so results are
+// deterministic; the noise and transit passes walk
 // contiguous chunks of the time-ordered points, one per thread, and merge the bins
 // and transits that straddle chunk ends in thread order.
 #include <hip/hip_runtime.h>
@@ -37,27 +42,34 @@ namespace mi355bls {
 
 namespace {
 
-constexpr int kFitThreads = 256;
-constexpr int kFitWaves = kFitThreads / 64;
+// Workgroup shapes: 256 threads and ranges of up to 1024 epochs when every star of
+// the batch is short (several stars share a CU), else 512 threads and 4096 epochs
+// (one long star per CU, more waves on its fit).
+constexpr int64_t kFitSmallMaxPoints = 65536;
 constexpr int kNPar = 5;
 constexpr int kNSum = 21;  // 15 (A, upper triangle) + 5 (g) + chi^2
 constexpr double kQMin = 1e-6, kQMax = 1.0, kQinMax = 0.5, kQin0 = 0.2;
 constexpr double kLambda0 = 1e-3, kRelTol = 1e-10;
 constexpr int kMaxIter = 60;
 
+template <int NT, int NE>  // threads, transit epochs whose fit-point ranges LDS holds
 struct FitLds {
-  double part[kFitWaves][kNSum];
+  static constexpr int kThreads = NT, kWaves = NT / 64, kEpochs = NE, kEpochsPerThread = NE / NT;
+  int32_t elo[NE];       // first point of each epoch's fit range
+  int32_t ecum[NE + 1];  // fit-range points before each epoch (exclusive prefix)
+  int32_t ewave[NT / 64];
+  double part[NT / 64][kNSum];
   double sum[kNSum];
   double th[kNPar], th2[kNPar];
   int go, accept;
   // noise and transit passes: one record per thread
-  int64_t hb[kFitThreads], tb[kFitThreads];        // head / tail bin ids (-1: empty chunk)
-  double hs[kFitThreads], ts[kFitThreads];
-  int64_t hc[kFitThreads], tc[kFitThreads];
-  int single[kFitThreads];
-  double wn[kFitThreads], wm[kFitThreads], wq[kFitThreads];  // interior bins: count, mean, M2
-  double rn[kFitThreads], rm[kFitThreads], rq[kFitThreads];  // residuals: count, mean, M2
-  int64_t ef[kFitThreads], el[kFitThreads], ec[kFitThreads], nt[kFitThreads];
+  int64_t hb[NT], tb[NT];        // head / tail bin ids (-1: empty chunk)
+  double hs[NT], ts[NT];
+  int64_t hc[NT], tc[NT];
+  int single[NT];
+  double wn[NT], wm[NT], wq[NT];  // interior bins: count, mean, M2
+  double rn[NT], rm[NT], rq[NT];  // residuals: count, mean, M2
+  int64_t ef[NT], el[NT], ec[NT], nt[NT];
 };
 
 __device__ __forceinline__ double time_from_mid(double t, double T0, double P) {
@@ -107,7 +119,8 @@ __device__ __forceinline__ double model_only(double t, double P, const double* t
 
 // Sum of v[0..nv) over the workgroup into L.sum (fixed order: lanes by shuffles,
 // then waves in order).
-__device__ void block_sums(double* v, int nv, FitLds& L) {
+template <class LDS>
+__device__ void block_sums(double* v, int nv, LDS& L) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int i = 0; i < nv; ++i) {
     double x = v[i];
@@ -118,7 +131,7 @@ __device__ void block_sums(double* v, int nv, FitLds& L) {
   __syncthreads();
   if (threadIdx.x < nv) {
     double x = 0.0;
-    for (int w = 0; w < kFitWaves; ++w) x += L.part[w][threadIdx.x];
+    for (int w = 0; w < LDS::kWaves; ++w) x += L.part[w][threadIdx.x];
     L.sum[threadIdx.x] = x;
   }
   __syncthreads();
@@ -175,11 +188,14 @@ __device__ __forceinline__ void chan_merge(double& n, double& m, double& q, doub
 
 }  // namespace
 
-__global__ void __launch_bounds__(kFitThreads) k_fit(const StarDesc* __restrict__ stars, const double* __restrict__ t,
+template <int NT, int NE>
+__global__ void __launch_bounds__(NT) k_fit(const StarDesc* __restrict__ stars, const double* __restrict__ t,
                                                      const double* __restrict__ y, const double* __restrict__ w,
                                                      const bls_result* __restrict__ res, double snr_min,
                                                      double pink_min, bls_fit_result* __restrict__ out) {
-  __shared__ FitLds L;
+  using LDS = FitLds<NT, NE>;
+  constexpr int kFitThreads = NT, kFitWaves = NT / 64, kFitEpochs = NE, kEpochsPerThread = LDS::kEpochsPerThread;
+  __shared__ LDS L;
   const int tid = threadIdx.x;
   const StarDesc d = stars[blockIdx.x];
   const int64_t n = d.n, off = d.p_off;
@@ -199,14 +215,80 @@ __global__ void __launch_bounds__(kFitThreads) k_fit(const StarDesc* __restrict_
     return;
   }
   const double D0 = qb * P;
+  // ---- fit-point ranges, one per transit epoch (windows of half-width 2 D0 < P/4
+  // apart by more than their width, so no point is in two)
+  const double half = 2.0 * D0;
+  const double t_lo = t[off], t_hi = t[off + n - 1];
+  const int64_t ep0 = static_cast<int64_t>(floor((t_lo - T0b) / P + 0.5)) - 1;
+  const int64_t ep1 = static_cast<int64_t>(floor((t_hi - T0b) / P + 0.5)) + 1;
+  const int64_t n_ep = ep1 - ep0 + 1;
+  const bool ranged = half < 0.25 * P && n_ep >= 1 && n_ep <= kFitEpochs && n < (int64_t(1) << 31);
+  if (ranged) {
+    const double margin = 1e-6;  // days; the per-point test decides
+    int32_t cnt[kEpochsPerThread];
+    int32_t mine = 0;
+    for (int k = 0; k < kEpochsPerThread; ++k) {
+      const int64_t e = static_cast<int64_t>(tid) * kEpochsPerThread + k;
+      cnt[k] = 0;
+      if (e >= n_ep) continue;
+      const double c = T0b + static_cast<double>(ep0 + e) * P;
+      const double a = c - half - margin, b = c + half + margin;
+      int64_t lo = 0, hi = n;  // first index with t >= a
+      while (lo < hi) {
+        const int64_t m = (lo + hi) >> 1;
+        if (t[off + m] < a) lo = m + 1; else hi = m;
+      }
+      int64_t lo2 = lo, hi2 = n;  // first index with t > b
+      while (lo2 < hi2) {
+        const int64_t m = (lo2 + hi2) >> 1;
+        if (t[off + m] <= b) lo2 = m + 1; else hi2 = m;
+      }
+      L.elo[e] = static_cast<int32_t>(lo);
+      cnt[k] = static_cast<int32_t>(lo2 - lo);
+      mine += cnt[k];
+    }
+    // exclusive prefix of the per-thread totals (waves by shuffles, then the waves)
+    const int lane = tid & 63, wave = tid >> 6;
+    int32_t incl = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t yv = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += yv;
+    }
+    if (lane == 63) L.ewave[wave] = incl;
+    __syncthreads();
+    int32_t before = 0;
+    for (int v = 0; v < wave; ++v) before += L.ewave[v];
+    int32_t acc = before + incl - mine;
+    for (int k = 0; k < kEpochsPerThread; ++k) {
+      const int64_t e = static_cast<int64_t>(tid) * kEpochsPerThread + k;
+      if (e < n_ep) L.ecum[e] = acc;
+      acc += cnt[k];
+    }
+    if (tid == kFitThreads - 1) L.ecum[n_ep] = acc;
+    __syncthreads();
+  }
+  // Calls body(i) for the star's candidate fit points, i in a fixed per-thread order.
+  auto for_fit = [&](auto&& body) {
+    if (!ranged) {
+      for (int64_t i = tid; i < n; i += kFitThreads) body(i);
+      return;
+    }
+    const int32_t total = L.ecum[n_ep];
+    int64_t e = 0;
+    for (int32_t j = tid; j < total; j += kFitThreads) {
+      while (L.ecum[e + 1] <= j) ++e;
+      body(static_cast<int64_t>(L.elo[e]) + (j - L.ecum[e]));
+    }
+  };
   // ---- starting level: weighted mean of the fit points outside the starting box
   {
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // sum w y, sum w (outside); sum w y, sum w (all); count
-    for (int64_t i = tid; i < n; i += kFitThreads) {
+    for_fit([&](int64_t i) {
       const double wi = w ? w[off + i] : 1.0;
-      if (!(wi > 0.0)) continue;
+      if (!(wi > 0.0)) return;
       const double a = fabs(time_from_mid(t[off + i], T0b, P));
-      if (!(a <= 2.0 * D0)) continue;
+      if (!(a <= 2.0 * D0)) return;
       const double yi = y[off + i];
       v[2] += wi * yi;
       v[3] += wi;
@@ -215,7 +297,7 @@ __global__ void __launch_bounds__(kFitThreads) k_fit(const StarDesc* __restrict_
         v[0] += wi * yi;
         v[1] += wi;
       }
-    }
+    });
     block_sums(v, 5, L);
   }
   const int64_t nfit = static_cast<int64_t>(L.sum[4]);
@@ -245,11 +327,11 @@ __global__ void __launch_bounds__(kFitThreads) k_fit(const StarDesc* __restrict_
       for (int k = 0; k < kNSum; ++k) v[k] = 0.0;
       double th[kNPar];
       for (int k = 0; k < kNPar; ++k) th[k] = L.th[k];
-      for (int64_t i = tid; i < n; i += kFitThreads) {
+      for_fit([&](int64_t i) {
         const double wi = w ? w[off + i] : 1.0;
-        if (!(wi > 0.0)) continue;
+        if (!(wi > 0.0)) return;
         const double ti = t[off + i];
-        if (!(fabs(time_from_mid(ti, T0b, P)) <= 2.0 * D0)) continue;
+        if (!(fabs(time_from_mid(ti, T0b, P)) <= 2.0 * D0)) return;
         double J[kNPar];
         const double res_i = y[off + i] - model_jac(ti, P, th, J);
         int e = 0;
@@ -257,7 +339,7 @@ __global__ void __launch_bounds__(kFitThreads) k_fit(const StarDesc* __restrict_
           for (int b = a; b < kNPar; ++b) v[e++] += wi * J[a] * J[b];
         for (int a = 0; a < kNPar; ++a) v[15 + a] += wi * J[a] * res_i;
         v[20] += wi * res_i * res_i;
-      }
+      });
       block_sums(v, kNSum, L);
       if (tid == 0) {
         int e = 0;
@@ -308,14 +390,14 @@ __global__ void __launch_bounds__(kFitThreads) k_fit(const StarDesc* __restrict_
       double v[1] = {0.0};
       double th2[kNPar];
       for (int k = 0; k < kNPar; ++k) th2[k] = L.th2[k];
-      for (int64_t i = tid; i < n; i += kFitThreads) {
+      for_fit([&](int64_t i) {
         const double wi = w ? w[off + i] : 1.0;
-        if (!(wi > 0.0)) continue;
+        if (!(wi > 0.0)) return;
         const double ti = t[off + i];
-        if (!(fabs(time_from_mid(ti, T0b, P)) <= 2.0 * D0)) continue;
+        if (!(fabs(time_from_mid(ti, T0b, P)) <= 2.0 * D0)) return;
         const double ri = y[off + i] - model_only(ti, P, th2);
         v[0] += wi * ri * ri;
-      }
+      });
       block_sums(v, 1, L);
     }
     const double chi2b = L.sum[0];
@@ -527,8 +609,14 @@ extern "C" bls_status bls_fit(bls_plan* plan, void* ws, const double* d_t, const
   if (!ws || plan->uploaded_to != ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return BLS_E_STATE;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const StarDesc* sd = reinterpret_cast<const StarDesc*>(static_cast<char*>(ws) + plan->layout.stars);
-  hipLaunchKernelGGL(k_fit, dim3(plan->n_stars), dim3(kFitThreads), 0, st, sd, d_t, d_y, d_w, d_result, snr_min,
-                     pink_min, d_fit);
+  int64_t n_max = 0;
+  for (const StarDesc& d : plan->stars) n_max = d.n > n_max ? d.n : n_max;
+  if (n_max <= kFitSmallMaxPoints)
+    hipLaunchKernelGGL((k_fit<256, 1024>), dim3(plan->n_stars), dim3(256), 0, st, sd, d_t, d_y, d_w, d_result,
+                       snr_min, pink_min, d_fit);
+  else
+    hipLaunchKernelGGL((k_fit<512, 4096>), dim3(plan->n_stars), dim3(512), 0, st, sd, d_t, d_y, d_w, d_result,
+                       snr_min, pink_min, d_fit);
   BLS_HIP_TRY(hipGetLastError());
   return BLS_OK;
 }
