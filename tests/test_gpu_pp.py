@@ -125,15 +125,17 @@ def test_backward_parity():
     loss = float(net.loss.cpu().numpy()[0])
     lo, go = P.loss_and_grad(list(X), theta, list(lag), list(labels))
     _say("loss gpu %.6f oracle %.6f" % (loss, lo))
-    assert abs(loss - lo) <= 1e-3 * abs(lo)
+    assert abs(loss - lo) <= 1e-5 * abs(lo)
     for name, (a, b_) in P.OFF.items():
         ga, gb = g[a:b_], go[a:b_]
         scale = max(float(np.max(np.abs(gb))), 1e-12)
         err = np.abs(ga - gb) / scale
         _say("grad %-5s element-wise: max |gpu - oracle| / max|oracle| %.2e, elements above 1e-5: %d of %d"
              % (name, err.max(), int(np.sum(err > 1e-5)), len(err)))
-        # every element, not a norm: a wrong tap anywhere in a group fails
-        assert err.max() <= 1e-4, name
+        # every element, not a norm: a wrong tap anywhere in a group fails (observed
+        # at most 1.3e-6: FP32 accumulation of the backward against FP64, with the
+        # BF16 activations rounded the same way on both sides)
+        assert err.max() <= 1e-5, name
     # deterministic: same gradient bits on a second evaluation
     g1 = net.grad.clone()
     net.gradient(xd, ld, tgt)
