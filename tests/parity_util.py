@@ -5,6 +5,9 @@ import math
 import numpy as np
 
 SR_RTOL = 1e-5          # contract: SR within 1e-5 relative of the FP64 oracle
+EXACT_SR_RTOL = 1e-11   # the plain path's exact int64 bin sums: observed at most 6.5e-14
+                        # (full-size sector stars); a dropped or misquantised point
+                        # is far above this
 NEAR_TIE_RTOL = 1e-12   # an index or (m, j) that differs must be a near-tie of the oracle's values
 
 
@@ -53,7 +56,8 @@ def _check_argmax(label, what, i_gpu, i_orc, spec_orc):
 
 
 def compare_star(ds, orc, s_gpu, s_orc, batch_star, label="", geom=None):
-    """Compare one star's spectrum and summary; returns stats dict.  ``geom(f, m)``
+    """Compare one star's spectrum and summary (plain path, exact bin sums: SR within
+    EXACT_SR_RTOL); returns stats dict.  ``geom(f, m)``
     maps a best-window record to (bins, window length) where that is not (the
     oracle's nb, m), e.g. for the per-duration rebinning (m holds the duration index)."""
     sl = ds.star_slice(s_gpu)
@@ -65,7 +69,7 @@ def compare_star(ds, orc, s_gpu, s_orc, batch_star, label="", geom=None):
     rel = np.abs(sr_g - sr_o) / denom
     rel[(sr_o == 0) & (sr_g == 0)] = 0.0
     worst = float(rel.max())
-    assert worst <= SR_RTOL, "%s: SR max rel err %.3e at %d" % (label, worst, int(rel.argmax()))
+    assert worst <= EXACT_SR_RTOL, "%s: SR max rel err %.3e at %d" % (label, worst, int(rel.argmax()))
     if ds.best is not None:
         bg = ds._best_host[sl]
         mm = np.nonzero((bg["m"] != orc["m"][o0:o1]) | (bg["j"] != orc["j"][o0:o1]))[0]

@@ -57,7 +57,7 @@ def test_sector_batch_full_size(oracle, batch, precision):
     _say("case sector batch: %d stars, %d points, precision %d" % (b.n_stars, b.n_points, precision))
     ds = pu.fetch(pu.run_gpu(b, _lib.default_params(precision=precision)))
     sr_all, best_all, res = ds._sr_host, ds._best_host, ds._res_host
-    rel_tol = pu.SR_RTOL if precision == 0 else 2e-5
+    rel_tol = pu.EXACT_SR_RTOL if precision == 0 else 2e-5
     worst = 0.0
     for g in gold["stars"]:
         s = g["star"]

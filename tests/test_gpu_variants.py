@@ -90,7 +90,7 @@ def test_rebin_wide_bin_sets_in_passes(oracle):
     bb = ds.best_host()[:6]
     _say("case rebin passes: nb0 of the k=0 set", int(math.ceil(3.0 / (0.5 * oracle.qcirc(o.f[0], 3.0)))),
          "SR gpu", sr.tolist(), "oracle", o.sr.tolist())
-    np.testing.assert_allclose(sr, o.sr, rtol=pu.SR_RTOL, atol=0)
+    np.testing.assert_allclose(sr, o.sr, rtol=pu.EXACT_SR_RTOL, atol=0)
     geom = _geom(oracle, kw, 3.0)
     for i in range(6):
         if (bb["m"][i], bb["j"][i]) != (o.m[i], o.j[i]):
