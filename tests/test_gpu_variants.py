@@ -145,3 +145,32 @@ def test_rebin_stats_at_the_detection(oracle):
         _say("rebin stats star", s, got)
         for k in got:
             assert got[k] == o[k], (s, k, got[k], o[k])
+
+
+@pytest.mark.parametrize("case", ["exact_below_contact", "rebin_no_window"])
+def test_variant_edges(oracle, case):
+    """Periods below contact with the exact duration (the arcsine argument clamped at
+    1), and rebinning durations so long that some frequencies have no valid window."""
+    from paper_2302_01293_amd import _lib
+    b = synth.tiny(400, seed=11, span=6.0)
+    if case == "exact_below_contact":
+        kw, okw = dict(exact_duration=1), dict(exact_duration=1)
+        b.pmin[:] = 0.5 * oracle.period_at_a(1.0, 1.0)
+        b.pmax[:] = 2.0
+    else:
+        kw = okw = dict(rebin=1, qmin_fac=8.0, qmax_fac=9.0)
+        b.pmin[:] = 0.3
+        b.pmax[:] = 2.0
+    _say("case variant edge:", case, "points", b.n_points)
+    ds = pu.fetch(pu.run_gpu(b, _lib.default_params(**kw)))
+    orc = pu.run_oracle(oracle, b, okw=okw)
+    geom = None
+    if okw.get("rebin"):
+        g = oracle.rebin_ladder(oracle.params(**okw))
+
+        def geom(f, k):  # bins of set k with qmin_fac = 8
+            return int(math.ceil(3.0 / ((8.0 * oracle.qcirc(f, 1.0)) * g[int(k)]))), 3
+    st = pu.compare_star(ds, orc, 0, 0, b.star(0), case, geom=geom)
+    if case == "rebin_no_window":
+        assert np.any(ds._best_host["j"] == -1) and np.all(ds._sr_host[ds._best_host["j"] == -1] == 0.0)
+    _say(case, "max rel SR err", st["max_rel_sr"])

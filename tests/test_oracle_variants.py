@@ -174,3 +174,32 @@ def test_rebin_noiseless_box_closed_form_and_decode(oracle):
     if ii == i:
         assert (k_, j_, nb_) == (kstar, j0, nbk)
         assert abs(res["depth"] - depth) <= 1e-12 * depth
+
+
+def test_exact_duration_below_contact_is_clamped(oracle):
+    # an explicit minimum period below a = R* (R*/a > 1 at the highest frequencies):
+    # the duty cycle stops at asin(1) / pi = 1/2, never NaN, and the counts stay
+    # the fewest covering bins (never more than the small-angle count)
+    t = _star(span=10.0)
+    p_contact = oracle.period_at_a(1.0, 1.0)
+    pe = oracle.params(exact_duration=1)
+    f, nb, _ = oracle.grid(t, None, 1.0, pe, pmin=0.5 * p_contact, pmax=2.0)
+    fs, nbs, _ = oracle.grid(t, None, 1.0, oracle.params(), pmin=0.5 * p_contact, pmax=2.0)
+    assert f[-1] > 1.0 / p_contact                      # the grid reaches below contact
+    assert oracle.qcirc_exact(f[-1], 1.0) == 0.5
+    assert np.all(nb >= 1) and np.all(nb <= nbs)
+    qlo = np.maximum([0.5 * oracle.qcirc_exact(x, 1.0) for x in f], [0.5 * oracle.qcirc(x, 1.0) for x in f])
+    assert np.all(3.0 / nb <= qlo * (1 + 1e-15))
+
+
+def test_rebin_without_a_valid_window(oracle):
+    # a frequency whose every bin set has at most noverlap bins (durations of a third
+    # of the period or more) has no window: SR 0, k 0, j -1, nb of the k = 0 set
+    b = synth.tiny(20, seed=3, span=3.0)
+    t, y, w = b.star(0)
+    p = oracle.params(rebin=1, qmin_fac=8.0, qmax_fac=9.0)
+    sp = oracle.bls_star(t, y, w, 1.0, p, pmin=0.3, pmax=1.0)
+    qlo = np.array([8.0 * oracle.qcirc(x, 1.0) for x in sp.f])
+    none = np.ceil(3.0 / qlo) <= 3
+    assert none.any()
+    assert np.all(sp.sr[none] == 0.0) and np.all(sp.j[none] == -1) and np.all(sp.m[none] == 0)
