@@ -59,6 +59,7 @@ struct TrendLds {
   SelShared sh;
   int64_t start[kMaxSturges + 1];
   double kx[kMaxSturges], ky[kMaxSturges];
+  double slope[kMaxSturges];  // (ky[q+1] - ky[q]) / (kx[q+1] - kx[q]), once per knot pair
   int nk;
   ArgMax red[16];
 };
@@ -76,13 +77,22 @@ __device__ void build_knots(const StarDesc& d, const double* __restrict__ sr, Tr
     if (k < 0) k = 0;
     return k;
   };
-  // Bin b covers indices [start[b], start[b+1]) (bins are monotone in i).
-  for (int b = tid; b <= nbins; b += T) L.start[b] = nf;
-  __syncthreads();
-  for (int64_t i = tid; i < nf; i += T) {
-    const int k = bin_of(i);
-    const int kp = i > 0 ? bin_of(i - 1) : -1;
-    for (int b = kp + 1; b <= k; ++b) L.start[b] = i;
+  // Bin b covers indices [start[b], start[b+1]) (bins are monotone in i): start[b]
+  // is the first index whose bin is b or more, found by a binary search over i (the
+  // same bin_of as a pass over every frequency would evaluate).
+  for (int b = tid; b <= nbins; b += T) {
+    int64_t lo = 0, hi = nf;
+    if (b == 0) {
+      hi = 0;
+    } else if (b == nbins) {
+      lo = nf;
+    } else {
+      while (lo < hi) {
+        const int64_t m = (lo + hi) >> 1;
+        if (bin_of(m) < b) lo = m + 1; else hi = m;
+      }
+    }
+    L.start[b] = lo;
   }
   __syncthreads();
   if (tid == 0) L.nk = 0;
@@ -99,6 +109,8 @@ __device__ void build_knots(const StarDesc& d, const double* __restrict__ sr, Tr
     }
     __syncthreads();
   }
+  for (int q = tid; q + 1 < L.nk; q += T) L.slope[q] = (L.ky[q + 1] - L.ky[q]) / (L.kx[q + 1] - L.kx[q]);
+  __syncthreads();
 }
 
 // Linear interpolation through the knots, constant beyond the first and last.
@@ -108,8 +120,7 @@ __device__ double trend_at(const TrendLds& L, double f) {
   if (f >= L.kx[nk - 1]) return L.ky[nk - 1];
   int q = 0;
   while (q + 1 < nk && L.kx[q + 1] <= f) ++q;
-  const double slope = (L.ky[q + 1] - L.ky[q]) / (L.kx[q + 1] - L.kx[q]);
-  return slope * (f - L.kx[q]) + L.ky[q];
+  return L.slope[q] * (f - L.kx[q]) + L.ky[q];
 }
 
 // Residual rho = SR - trend into the scratch array, and sigma = 1.4826 MAD.
