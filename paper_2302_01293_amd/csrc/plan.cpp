@@ -337,8 +337,8 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
   pos = align256(pos + 8 * plan->n_points);
   L.rho = pos;
   pos = align256(pos + 8 * plan->n_freq);
-  L.counter = pos;  // 8 work-queue counters, 64 bytes apart
-  pos = align256(pos + 8 * 64);
+  L.counter = pos;  // 8 work-queue counters, 64 bytes apart, then the batch's flags word
+  pos = align256(pos + 9 * 64);
   L.total = pos;
   *out = plan;
   return BLS_OK;

@@ -78,7 +78,9 @@ struct StarRt {
   int64_t cw_total;  // sum of fixed-point weights (units of 2^-62); packed: the packed total
   int64_t cs_total;  // sum of fixed-point weighted residuals (units of s_scale); packed: 0
   double s_scale;    // 2^-e: value of one unit of the residual fixed point
-  double pad;
+  int64_t w_unit;    // precision 0: the common fixed-point weight when every point of
+                     // nonzero weight has the same one (then CW[n] = w_unit times the
+                     // number of such points before n), else 0; packed: 0
 };
 
 // Packed fixed point (precision 1): w~ in units of 2^-27 in the high 28 bits and

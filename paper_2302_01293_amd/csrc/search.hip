@@ -33,6 +33,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "plan.hpp"
 
@@ -84,6 +85,21 @@ __device__ T block_sum(T v, T* scratch) {
   }
   __syncthreads();
   r = scratch[0];
+  __syncthreads();
+  return r;
+}
+
+// Block reduction of one value per thread with an associative, commutative op.
+template <typename T, typename Op>
+__device__ T block_reduce(T v, T* scratch, Op op) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if (lane == 0) scratch[wave] = v;
+  __syncthreads();
+  T r = scratch[0];
+  for (int q = 1; q < static_cast<int>(blockDim.x >> 6); ++q) r = op(r, scratch[q]);
   __syncthreads();
   return r;
 }
@@ -167,6 +183,9 @@ __device__ double block_csum(CSum v, CSum* scratch) {
   return r.s + r.c;
 }
 
+// Kinds of star in a prepared batch (precision 0), or-ed into one flags word.
+constexpr unsigned kHasEqualWeights = 1u, kHasUnequalWeights = 2u;
+
 // ----------------------------------------------------------------------------
 // Preparation: one workgroup per star.
 //   W = sum w, wt = w / W, ybar = sum wt y (both compensated), x = y - ybar,
@@ -181,7 +200,7 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const StarDesc* __restrict
                                                       const double* __restrict__ t, const double* __restrict__ y,
                                                       const double* __restrict__ w, double* __restrict__ dt_out,
                                                       int64_t* __restrict__ cw_out, int64_t* __restrict__ cs_out,
-                                                      int32_t packed) {
+                                                      int32_t packed, unsigned int* __restrict__ flags) {
   __shared__ CSum sc[16];
   __shared__ double sd[16];
   __shared__ unsigned long long si[32];
@@ -210,6 +229,7 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const StarDesc* __restrict
   const int es = (packed ? 34 : 62) - e;
 
   unsigned long long carry_w = 0, carry_s = 0;
+  unsigned long long qmin = ~0ull, qmax = 0ull;  // nonzero fixed-point weights (precision 0)
   for (int64_t base = 0; base < n; base += T) {
     const int64_t i = base + tid;
     unsigned long long qw = 0, qs = 0;
@@ -222,6 +242,10 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const StarDesc* __restrict
       } else {
         qw = static_cast<unsigned long long>(static_cast<long long>(rint(ldexp(wt, 62))));
         qs = static_cast<unsigned long long>(sq);
+        if (qw != 0ull) {
+          qmin = min(qmin, qw);
+          qmax = max(qmax, qw);
+        }
       }
     }
     unsigned long long tw, ts = 0;
@@ -236,13 +260,22 @@ __global__ void __launch_bounds__(kThreads) k_prepare(const StarDesc* __restrict
     carry_w += tw;
     carry_s += ts;
   }
+  // One fixed-point weight for every weighted point (equal weights, zeros aside):
+  // the search may then accumulate counts of points instead of weight prefixes.
+  int64_t w_unit = 0;
+  if (!packed) {
+    qmin = block_reduce(qmin, si, [](unsigned long long x, unsigned long long z) { return min(x, z); });
+    qmax = block_reduce(qmax, si, [](unsigned long long x, unsigned long long z) { return max(x, z); });
+    if (qmax != 0ull && qmin == qmax && n < (int64_t{1} << 31)) w_unit = static_cast<int64_t>(qmax);
+  }
   if (tid == 0) {
     StarRt r;
     r.cw_total = static_cast<int64_t>(carry_w);
     r.cs_total = static_cast<int64_t>(carry_s);
     r.s_scale = ldexp(1.0, -es);
-    r.pad = 0.0;
+    r.w_unit = w_unit;
     rt[blockIdx.x] = r;
+    if (!packed) atomicOr(flags, w_unit != 0 ? kHasEqualWeights : kHasUnequalWeights);
   }
 }
 
@@ -354,6 +387,39 @@ __device__ __forceinline__ void lds_sub64(unsigned char* base, uint32_t byte_off
   atomicAdd(reinterpret_cast<unsigned long long*>(base + byte_off), 0ull - static_cast<unsigned long long>(v));
 }
 
+// Counts of weighted points (equal weights): a 32-bit add into the low word of the
+// bin's 8-byte slot.  A 32-bit LDS atomic issues in about two thirds of the time of
+// a 64-bit one on gfx950, and telescoped differences of counts are exact modulo 2^32.
+__device__ __forceinline__ void lds_add64(unsigned char* base, uint32_t byte_off, uint32_t v) {
+  atomicAdd(reinterpret_cast<unsigned int*>(base + byte_off), v);
+}
+
+__device__ __forceinline__ void lds_sub64(unsigned char* base, uint32_t byte_off, uint32_t v) {
+  atomicAdd(reinterpret_cast<unsigned int*>(base + byte_off), 0u - v);
+}
+
+// Exact division of a weight prefix v = count * unit by the star's common weight
+// (count < 2^32): with unit = 2^shift * odd, v >> shift = count * odd, and
+// multiplying by the inverse of odd modulo 2^32 leaves count modulo 2^32, which is
+// count.  The inverse comes from Newton's iteration x <- x (2 - odd x), which
+// doubles the number of correct low bits from the 3 of x = odd.
+struct CountDiv {
+  uint32_t shift, inv;
+};
+
+__device__ __forceinline__ CountDiv count_div(int64_t unit) {
+  const uint64_t u = static_cast<uint64_t>(unit);
+  const uint32_t t = static_cast<uint32_t>(__builtin_ctzll(u));
+  const uint32_t odd = static_cast<uint32_t>(u >> t);
+  uint32_t x = odd;
+  for (int i = 0; i < 4; ++i) x *= 2u - odd * x;
+  return CountDiv{t, x};
+}
+
+__device__ __forceinline__ uint32_t count_of(long long v, CountDiv c) {
+  return static_cast<uint32_t>(static_cast<uint64_t>(v) >> c.shift) * c.inv;
+}
+
 // Slot index -> (frequency k, bin b) for idx < F * stride <= 4096: a float
 // estimate of idx / stride corrected by one step either way.
 __device__ __forceinline__ void slot_of(int idx, int stride, float inv_stride, int& k, int& b) {
@@ -378,9 +444,11 @@ constexpr int kTelescope = 0, kDiff = 1;
 
 // One pass of the fold over the wave's block for frequencies k0 and, when TWO,
 // k0 + 1: a point whose bin differs from its predecessor's is a boundary.
-template <bool TWO, bool PACKED, int UM, int ARR>
+// WV: the weight values held per point (long long: prefixes CW; uint32_t: counts of
+// weighted points, equal weights).
+template <bool TWO, bool PACKED, int UM, int ARR, typename WV>
 __device__ __forceinline__ void fold_pass(unsigned char* smem, int stride, int k0, const GroupLds* g,
-                                          const double (&dtr)[UM], const long long (&cwr)[UM],
+                                          const double (&dtr)[UM], const WV (&cwr)[UM],
                                           const long long (&csr)[UM], double dt_before, int run, int form) {
   const int k1 = TWO ? k0 + 1 : k0;
   const double fa = g->f[k0], fb = g->f[k1];
@@ -476,9 +544,17 @@ constexpr int kXcds = 8;
 constexpr int kQueueChunk = 16;
 constexpr int kCounterStride = 16;  // 64 bytes between counters
 
+// After the counters: which kinds of star the prepared batch holds (precision 0),
+// set by k_prepare and read by the exact telescoping launches.
+constexpr int kFlagsIndex = kXcds * kCounterStride;
+
 // Zero the work counters on the stream (a kernel, so the sequence can be captured).
 __global__ void k_reset(unsigned int* next) {
   if (threadIdx.x < kXcds) next[threadIdx.x * kCounterStride] = 0u;
+}
+
+__global__ void k_clear_flags(unsigned int* next) {
+  if (threadIdx.x == 0) next[kFlagsIndex] = 0u;
 }
 
 // Packed total -> (weight units, residual units).
@@ -849,8 +925,9 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
 // DIP: only windows with s < 0 (dips) count.  BIG: the large workgroup shape, for
 // the frequencies whose fine-bin count lies in (kNbLimit, kNbLimitBig] and for every
 // frequency up to kNbLimitBig bins of stars with more than big_points points.
-template <bool PACKED, bool DFORM, bool DIP, bool BIG, bool EXQ>
+template <bool PACKED, bool DFORM, bool DIP, bool BIG, bool EXQ, bool CNT>
 __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search(SearchArgs a) {
+  static_assert(!CNT || (!PACKED && !DFORM), "counts replace the weight prefixes of the exact telescoping form");
   using W = Win<BIG>;
   extern __shared__ __align__(16) unsigned char smem[];
   long long* GW = reinterpret_cast<long long*>(smem);
@@ -865,6 +942,12 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
   const int m_max = a.c.m_max;
   const uint32_t m_mask = a.c.m_mask;
 
+  // Exact telescoping form: the stars of equal weights (counts) and the others run
+  // in separate launches; k_prepare flags which kinds the batch holds, so a launch
+  // with nothing to do ends here.
+  if constexpr (!PACKED && !DFORM) {
+    if ((a.next[kFlagsIndex] & (CNT ? kHasEqualWeights : kHasUnequalWeights)) == 0u) return;
+  }
   int queue = static_cast<int>(blockIdx.x % kXcds);  // used by thread 0 only
   int probes = 0;
   WorkItem it;
@@ -879,6 +962,14 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
     const bool long_star = d.n > a.c.big_points;
     if (!BIG && long_star) continue;
     const StarRt rt = a.rt[it.star];
+    // Equal weights: CW[n] is the common weight times the number of weighted points
+    // before n, so G_W accumulates those counts in 32 bits (telescoped differences
+    // are exact modulo 2^32, every count is below 2^31) and H_W is rebuilt from them.
+    if constexpr (!PACKED && !DFORM) {
+      if ((rt.w_unit != 0) != CNT) continue;  // the other launch's star
+    }
+    constexpr bool cnt = CNT;
+    const CountDiv inv_unit = cnt ? count_div(rt.w_unit) : CountDiv{0u, 0u};
     const double w_unit = PACKED ? packed_w_unit(rt) : 0.0;  // packed: 1 / quantised total weight
     const int64_t n = d.n;
     const double* __restrict__ dt = a.dt + d.p_off;
@@ -913,7 +1004,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
       const int32_t q = a.gaps[d.g_off + tid];
       g->gdt0[tid] = dt[q - 1];
       g->gdt1[tid] = dt[q];
-      g->gcw[tid] = cw[q];
+      g->gcw[tid] = cnt ? static_cast<long long>(count_of(cw[q], inv_unit)) : cw[q];
       g->gcs[tid] = PACKED ? 0 : cs[q];
     }
 
@@ -971,13 +1062,17 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
         if (wbase >= n) continue;
         const int64_t wend = min<int64_t>(n, wbase + static_cast<int64_t>(64) * run);
         double dtr[UM];
-        long long cwr[UM], csr[UM];
+        std::conditional_t<CNT, uint32_t, long long> cwr[UM];
+        long long csr[UM];
         // Points past the block's end repeat its last point: same bin, no boundary.
 #pragma unroll
         for (int u = 0; u < UM; ++u) {
           const int64_t q = min<int64_t>(wbase + u * 64 + ((u & 1) ? 63 - lane : lane), wend - 1);
           dtr[u] = dt[q];
-          cwr[u] = cw[q];
+          if constexpr (CNT)
+            cwr[u] = count_of(cw[q], inv_unit);
+          else
+            cwr[u] = cw[q];
           csr[u] = PACKED ? 0 : cs[q];
         }
         const double dt_before = dt[wbase > 0 ? wbase - 1 : 0];
@@ -1001,6 +1096,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
         const int32_t nb = __builtin_amdgcn_readfirstlane(g->nb[k]);
         const int32_t bl = g->blast[k];
         const int mrep = min(m_max, nb - 1);
+        const uint32_t count_total = cnt ? count_of(rt.cw_total, inv_unit) : 0u;
         long long* gw = GW + k * stride;
         long long* gs = GS + k * stride;
         const long long g0w = gw[0], g0s = PACKED ? 0 : gs[0];
@@ -1059,9 +1155,11 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
               ds = PACKED ? 0ull : static_cast<unsigned long long>(ns) - static_cast<unsigned long long>(gs[b]) + as;
             }
             if (b == bl) {
-              dw += static_cast<unsigned long long>(rt.cw_total);
+              dw += cnt ? static_cast<unsigned long long>(count_total) : static_cast<unsigned long long>(rt.cw_total);
               ds += static_cast<unsigned long long>(rt.cs_total);
             }
+            // counts (low words; the slots' high words stay zero) -> weight prefixes
+            if (cnt) dw = static_cast<unsigned long long>(static_cast<uint32_t>(dw)) * static_cast<unsigned long long>(rt.w_unit);
             double vw, vs;
             if (PACKED) {
               unpack(dw, rt.s_scale, w_unit, vw, vs);
@@ -1260,33 +1358,39 @@ extern "C" bls_status bls_prepare(bls_plan* plan, void* ws, const double* d_t, c
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   const Layout& L = plan->layout;
+  unsigned int* counters = reinterpret_cast<unsigned int*>(base + L.counter);
+  hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, st, counters);
+  BLS_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_prepare, dim3(plan->n_stars), dim3(kThreads), 0, st,
                      reinterpret_cast<const StarDesc*>(base + L.stars), reinterpret_cast<StarRt*>(base + L.rt),
                      d_t, d_y, d_w, reinterpret_cast<double*>(base + L.dt), reinterpret_cast<int64_t*>(base + L.cw),
-                     reinterpret_cast<int64_t*>(base + L.cs), plan->consts.packed);
+                     reinterpret_cast<int64_t*>(base + L.cs), plan->consts.packed, counters + kFlagsIndex);
   BLS_HIP_TRY(hipGetLastError());
   return BLS_OK;
 }
 
+template <bool PACKED, bool DFORM, bool BIG, bool EXQ, bool CNT>
+static void launch_k(bool dip, const dim3& gd, const dim3& bd, size_t lds, hipStream_t st, const SearchArgs& a) {
+  if (dip) hipLaunchKernelGGL((k_search<PACKED, DFORM, true, BIG, EXQ, CNT>), gd, bd, lds, st, a);
+  else hipLaunchKernelGGL((k_search<PACKED, DFORM, false, BIG, EXQ, CNT>), gd, bd, lds, st, a);
+}
+
+// Accumulation forms of one launch: telescoping with weight prefixes, difference
+// form, telescoping with counts of weighted points (precision 0, equal weights).
+enum SearchForm { kFormPrefix = 0, kFormDiff = 1, kFormCount = 2 };
+
 template <bool BIG, bool EXQ>
-static void launch_search_x(bool packed, bool dform, bool dip, const dim3& gd, const dim3& bd, size_t lds,
+static void launch_search_x(bool packed, int form, bool dip, const dim3& gd, const dim3& bd, size_t lds,
                             hipStream_t st, const SearchArgs& a) {
   if (packed) {
-    if (dform) {
-      if (dip) hipLaunchKernelGGL((k_search<true, true, true, BIG, EXQ>), gd, bd, lds, st, a);
-      else hipLaunchKernelGGL((k_search<true, true, false, BIG, EXQ>), gd, bd, lds, st, a);
-    } else {
-      if (dip) hipLaunchKernelGGL((k_search<true, false, true, BIG, EXQ>), gd, bd, lds, st, a);
-      else hipLaunchKernelGGL((k_search<true, false, false, BIG, EXQ>), gd, bd, lds, st, a);
-    }
+    if (form == kFormDiff) launch_k<true, true, BIG, EXQ, false>(dip, gd, bd, lds, st, a);
+    else launch_k<true, false, BIG, EXQ, false>(dip, gd, bd, lds, st, a);
+  } else if (form == kFormDiff) {
+    launch_k<false, true, BIG, EXQ, false>(dip, gd, bd, lds, st, a);
+  } else if (form == kFormCount) {
+    launch_k<false, false, BIG, EXQ, true>(dip, gd, bd, lds, st, a);
   } else {
-    if (dform) {
-      if (dip) hipLaunchKernelGGL((k_search<false, true, true, BIG, EXQ>), gd, bd, lds, st, a);
-      else hipLaunchKernelGGL((k_search<false, true, false, BIG, EXQ>), gd, bd, lds, st, a);
-    } else {
-      if (dip) hipLaunchKernelGGL((k_search<false, false, true, BIG, EXQ>), gd, bd, lds, st, a);
-      else hipLaunchKernelGGL((k_search<false, false, false, BIG, EXQ>), gd, bd, lds, st, a);
-    }
+    launch_k<false, false, BIG, EXQ, false>(dip, gd, bd, lds, st, a);
   }
 }
 
@@ -1294,15 +1398,15 @@ static void launch_search_x(bool packed, bool dform, bool dip, const dim3& gd, c
 // form, dips only, exact durations), as a persistent grid of `groups` workgroups
 // per CU.
 template <bool BIG>
-static void launch_search(bool packed, bool dform, bool dip, bool exq, int64_t n_items, int cus, hipStream_t st,
+static void launch_search(bool packed, int form, bool dip, bool exq, int64_t n_items, int cus, hipStream_t st,
                           const SearchArgs& a) {
   const int64_t grid = std::min<int64_t>(n_items, Win<BIG>::groups * static_cast<int64_t>(cus));
   const dim3 gd(static_cast<unsigned>(grid)), bd(kSearchThreads);
   const size_t lds = search_lds<BIG>();
   if (exq)
-    launch_search_x<BIG, true>(packed, dform, dip, gd, bd, lds, st, a);
+    launch_search_x<BIG, true>(packed, form, dip, gd, bd, lds, st, a);
   else
-    launch_search_x<BIG, false>(packed, dform, dip, gd, bd, lds, st, a);
+    launch_search_x<BIG, false>(packed, form, dip, gd, bd, lds, st, a);
 }
 
 extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* d_windows, int64_t n_windows,
@@ -1338,19 +1442,26 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
   BLS_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   if (cus < 1) return BLS_E_HIP;
   // Persistent launches, each preceded by a reset of the work counters: the common
-  // shape, then (when the batch needs them) stars whose steps mostly skip fine bins
-  // in difference form, the large shape for frequencies with more fine bins, and
-  // the frequencies beyond one LDS pass.  Each launch skips the others' work.
+  // shape, then the large shape for frequencies with more fine bins, and the
+  // frequencies beyond one LDS pass.  Per shape: stars of equal weights with counts
+  // (precision 0; a launch ends at once when the batch has none, and likewise the
+  // next one when every star has equal weights), the other stars, and (when the
+  // batch needs it) stars whose steps mostly skip fine bins in difference form.
+  // Each launch skips the others' work.
   const bool packed = plan->consts.packed != 0, dip = a.c.dip_only != 0, exq = a.c.exact_q != 0;
   const bool dform = d_windows ? plan->has_dform_star : plan->has_dform;
+  int forms[3], n_forms = 0;
+  if (!packed) forms[n_forms++] = kFormCount;
+  forms[n_forms++] = kFormPrefix;
+  if (dform) forms[n_forms++] = kFormDiff;
   for (int big = 0; big < (plan->has_big ? 2 : 1); ++big) {
-    for (int df = 0; df < (dform ? 2 : 1); ++df) {
+    for (int fi = 0; fi < n_forms; ++fi) {
       hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.next);  // 8 counters
       BLS_HIP_TRY(hipGetLastError());
       if (big)
-        launch_search<true>(packed, df != 0, dip, exq, n_items, cus, st, a);
+        launch_search<true>(packed, forms[fi], dip, exq, n_items, cus, st, a);
       else
-        launch_search<false>(packed, df != 0, dip, exq, n_items, cus, st, a);
+        launch_search<false>(packed, forms[fi], dip, exq, n_items, cus, st, a);
       BLS_HIP_TRY(hipGetLastError());
     }
   }
