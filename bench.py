@@ -111,16 +111,29 @@ def measure_ceilings(copy_mib: int = 2048) -> dict:
     L = ctypes.CDLL(path)
     L.mi355_ceilings.restype = ctypes.c_int
     L.mi355_ceilings.argtypes = [ctypes.c_void_p, ctypes.c_int64]
-    out = np.zeros(8)
+    out = np.zeros(9)
     st = L.mi355_ceilings(out.ctypes.data, int(copy_mib) << 20)
     if st != 0:
         raise RuntimeError("mi355_ceilings failed (hipError %d)" % st)
     clk = out[7] * 1e9
     return {"dmul_simd_cycles": out[0], "fract_simd_cycles": out[1], "cvt_plus_xor_simd_cycles": out[2],
             "iadd_simd_cycles": out[3], "lds_add_u64_cu_cycles_64_lanes": out[4],
-            "lds_add_u64_cu_cycles_1_lane": out[5], "hbm_copy_GBps": out[6], "clock_GHz": out[7],
+            "lds_add_u64_cu_cycles_1_lane": out[5], "lds_add_u32_cu_cycles_64_lanes": out[8],
+            "hbm_copy_GBps": out[6], "clock_GHz": out[7],
             "fp64_ops_per_s": 1024 * 64 / out[0] * clk,
             "lds_atomic_instr_per_s": 256 / out[4] * clk}
+
+
+def equal_weights(batch) -> np.ndarray:
+    """Stars whose points of nonzero weight all carry the same weight: the search
+    accumulates counts of weighted points for them (their fixed-point weights are
+    then equal too)."""
+    out = np.zeros(batch.n_stars, bool)
+    for s in range(batch.n_stars):
+        w = batch.star(s)[2]
+        w = w[w > 0]
+        out[s] = len(w) > 0 and bool(np.all(w == w[0]))
+    return out
 
 
 def make_workload(name: str, n_stars: int, batch_stars: int, steps: int):
@@ -345,8 +358,9 @@ def main():
         pl = _lib.Plan(st.batch.t, st.batch.y, st.batch.w, st.batch.offsets, st.batch.rho,
                        st.batch.pmin, st.batch.pmax, params)
         nfs = np.diff(pl.freq_offsets)
-        sizes.append(dict(nf=int(pl.n_freq), ws=int(pl.workspace_bytes),
-                          cells=float(np.sum(nfs.astype(np.float64) * np.diff(st.batch.offsets)))))
+        star_cells = nfs.astype(np.float64) * np.diff(st.batch.offsets)
+        sizes.append(dict(nf=int(pl.n_freq), ws=int(pl.workspace_bytes), cells=float(np.sum(star_cells)),
+                          equal_weight_cells=float(np.sum(star_cells[equal_weights(st.batch)]))))
         if len(steps) == 1:
             st.plan = pl
         else:
@@ -508,14 +522,23 @@ def main():
         out["roofline"]["measured_peak"] = c["fp64_ops_per_s"] / 1e12
         out["roofline"]["frac_of_measured"] = achieved / (c["fp64_ops_per_s"] / 1e12)
         # The fold's other bound: each wave-step (64 points at one frequency) adds the
-        # boundary's two int64 prefix values to LDS with two ds_add_u64 whenever any
-        # of its lanes enters a new bin, which on these grids is every step (3-25
-        # points per bin visit); at the measured cycles per such instruction the
-        # LDS caps the search at this many cells/s.
-        cyc = c["lds_add_u64_cu_cycles_64_lanes"]
-        lds_cap = 256 * c["clock_GHz"] * 1e9 / (2.0 * cyc) * 64.0
+        # boundary's values to LDS whenever any of its lanes enters a new bin, which
+        # on these grids is every step (3-25 points per bin visit): two ds_add_u64
+        # (weight and residual prefixes), or one ds_add_u64 and one ds_add_u32 for
+        # stars of equal weights (counts of weighted points); at the measured cycles
+        # per such instruction, weighted by the cells of each kind of star, the LDS
+        # caps the search at this many cells/s.
+        c64, c32 = c["lds_add_u64_cu_cycles_64_lanes"], c["lds_add_u32_cu_cycles_64_lanes"]
+        if args.precision == 1:  # one packed 64-bit sum per boundary
+            cyc, basis = c64, "1 ds_add_u64 (packed sums) per 64-cell wave-step at %.2f CU-cycles" % c64
+        else:
+            eq = float(sum(sizes[k % n_batches]["equal_weight_cells"] for k in range(args.steps))) / cells
+            cyc = eq * (c64 + c32) + (1.0 - eq) * 2.0 * c64
+            basis = ("per 64-cell wave-step, ds_add_u64 (%.2f CU-cycles) + ds_add_u32 (%.2f) on the %.1f%% of cells "
+                     "in stars of equal weights, 2 ds_add_u64 on the rest" % (c64, c32, 100.0 * eq))
+        lds_cap = 256 * c["clock_GHz"] * 1e9 / cyc * 64.0
         out["roofline"]["lds_atomic_bound"] = {"cells_per_s": lds_cap, "frac": (cells / search_s) / lds_cap,
-                                               "basis": "2 ds_add_u64 per 64-cell wave-step at %.2f CU-cycles" % cyc}
+                                               "basis": basis}
         log("ceilings: DMUL %.2f FRACT %.2f SIMD-cycles per wave instruction; 64-bit LDS atomic %.2f CU-cycles; "
             "copy %.0f GB/s" % (c["dmul_simd_cycles"], c["fract_simd_cycles"], c["lds_add_u64_cu_cycles_64_lanes"],
                                 c["hbm_copy_GBps"]))

@@ -221,7 +221,10 @@ bls_status bls_plan_upload(bls_plan* plan, void* d_workspace, int64_t workspace_
  * sums), x = y - ybar; then dt = t - t0 and the exclusive prefix sums of wt and of
  * wt x in int64 fixed point, stored in the workspace.  Device inputs: packed t, y
  * (required) and w (nullable: unit weights), identical to the host arrays given to
- * bls_plan_create().  Must precede bls_search_batch() on the same stream. */
+ * bls_plan_create().  It also notes, per star, whether every point of nonzero weight
+ * carries the same fixed-point weight; bls_search_batch() then sums counts of such
+ * points in place of weight prefixes (the same integers once multiplied back, so the
+ * same results).  Must precede bls_search_batch() on the same stream. */
 bls_status bls_prepare(bls_plan* plan, void* d_workspace, const double* d_t, const double* d_y,
                        const double* d_w, bls_stream_t stream);
 

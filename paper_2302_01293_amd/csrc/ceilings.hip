@@ -4,7 +4,8 @@
 //   * FP64 multiply and fract (the fold's phase arithmetic), FP64 -> int32 convert;
 //   * 32-bit integer add (a plain VALU reference);
 //   * 64-bit LDS atomic add (the boundary accumulation), per wave instruction,
-//     with one and with all 64 lanes active;
+//     with one and with all 64 lanes active, and the 32-bit one (counts of
+//     weighted points when a star's weights are equal);
 //   * a device-to-device copy (HBM read + write).
 // Each kernel runs many independent chains on a full grid (8 waves per SIMD); the
 // rates are in wave instructions per SIMD cycle (VALU) or CU cycles per wave
@@ -84,22 +85,24 @@ __global__ void __launch_bounds__(kThreads) c_iadd(double* out, double) {
   out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
-// Two 64-bit LDS atomic adds per iteration on `active` lanes of each wave; every
-// address stays inside the 16 KB array.
+// Two LDS atomic adds of type U (64- or 32-bit) per iteration on `active` lanes of
+// each wave; every address stays inside the 16 KB array.
+template <typename U>
 __global__ void __launch_bounds__(kThreads) c_lds(double* out, int active) {
-  __shared__ unsigned long long g[2048];
-  for (int i = threadIdx.x; i < 2048; i += blockDim.x) g[i] = 0;
+  constexpr unsigned kN = 16384 / sizeof(U);
+  __shared__ U g[kN];
+  for (unsigned i = threadIdx.x; i < kN; i += blockDim.x) g[i] = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const unsigned off = threadIdx.x & 2047u;
+  const unsigned off = threadIdx.x & (kN - 1);
   for (int i = 0; i < kIters / 4; ++i) {
     if (lane < active) {
-      atomicAdd(&g[(off + i) & 2047u], 1ull);
-      atomicAdd(&g[(off + i + 512) & 2047u], 1ull);
+      atomicAdd(&g[(off + i) & (kN - 1)], U(1));
+      atomicAdd(&g[(off + i + kN / 4) & (kN - 1)], U(1));
     }
   }
   __syncthreads();
-  out[blockIdx.x * blockDim.x + threadIdx.x] = static_cast<double>(g[threadIdx.x & 2047u]);
+  out[blockIdx.x * blockDim.x + threadIdx.x] = static_cast<double>(g[threadIdx.x & (kN - 1)]);
 }
 
 __global__ void c_copy(const double4* __restrict__ src, double4* __restrict__ dst, int64_t n) {
@@ -110,10 +113,11 @@ __global__ void c_copy(const double4* __restrict__ src, double4* __restrict__ ds
 
 }  // namespace
 
-// out[0..7]: SIMD cycles per wave instruction of DMUL, FRACT, CVT+XOR, IADD; CU cycles
+// out[0..8]: SIMD cycles per wave instruction of DMUL, FRACT, CVT+XOR, IADD; CU cycles
 // per 64-bit LDS atomic wave instruction with 64 and with 1 active lane; HBM copy
-// GB/s (read + write) over `copy_bytes` (0 skips it); the clock in GHz.  Returns 0,
-// or the failing hipError_t.
+// GB/s (read + write) over `copy_bytes` (0 skips it); the clock in GHz; CU cycles per
+// 32-bit LDS atomic wave instruction with 64 active lanes.  Returns 0, or the
+// failing hipError_t.
 extern "C" int mi355_ceilings(double* out, int64_t copy_bytes) {
   int dev = 0, cus = 0, clk_khz = 0;
   hipError_t e;
@@ -150,10 +154,12 @@ extern "C" int mi355_ceilings(double* out, int64_t copy_bytes) {
   ms = timed([&] { hipLaunchKernelGGL(c_iadd, dim3(blocks), dim3(kThreads), 0, 0, buf, 1.0); });
   out[3] = ms * simd_cycles_per_ms / valu_instr;
   const double lds_instr = double(blocks) * (kThreads / 64) * (kIters / 4) * 2;
-  ms = timed([&] { hipLaunchKernelGGL(c_lds, dim3(blocks), dim3(kThreads), 0, 0, buf, 64); });
+  ms = timed([&] { hipLaunchKernelGGL(c_lds<unsigned long long>, dim3(blocks), dim3(kThreads), 0, 0, buf, 64); });
   out[4] = ms * 1e-3 * clk * cus / lds_instr;
-  ms = timed([&] { hipLaunchKernelGGL(c_lds, dim3(blocks), dim3(kThreads), 0, 0, buf, 1); });
+  ms = timed([&] { hipLaunchKernelGGL(c_lds<unsigned long long>, dim3(blocks), dim3(kThreads), 0, 0, buf, 1); });
   out[5] = ms * 1e-3 * clk * cus / lds_instr;
+  ms = timed([&] { hipLaunchKernelGGL(c_lds<unsigned int>, dim3(blocks), dim3(kThreads), 0, 0, buf, 64); });
+  out[8] = ms * 1e-3 * clk * cus / lds_instr;
   out[6] = 0.0;
   if (copy_bytes >= 32) {
     const int64_t n = copy_bytes / 32;

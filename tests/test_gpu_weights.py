@@ -2,8 +2,10 @@
 varies by a factor of two within a star, w_n = 1/sigma_n^2), stars of 1-13
 sectors at 200-s cadence.
 
-Exact mode (precision 0): the plain contract -- SR within 1e-5 of the FP64 oracle
-per frequency, best windows equal except at near-ties, argmax indices equal.
+Exact mode (precision 0): the plain contract -- SR within 1e-11 of the FP64 oracle
+per frequency, best windows equal except at near-ties, argmax indices equal; also
+for a batch mixing stars of equal weights (searched with counts of weighted
+points), zero-weight points and varied weights.
 Packed mode (precision 1): each point's normalised weight is quantised to 2^-27, so
 with unequal weights a window's weight fraction r carries a rounding of about
 2^-28 per point; the SR error against the oracle is reported as max / p99 /
@@ -31,6 +33,26 @@ def test_varied_weights_exact(oracle):
     for s in range(b.n_stars):
         worst = max(worst, pu.compare_star(ds, orc, s, s, b.star(s), "varied[%d]" % s)["max_rel_sr"])
     _say("varied weights max rel SR err", worst)
+
+
+def test_mixed_weight_kinds_exact(oracle):
+    """One batch holding stars of equal weights (searched with counts of weighted
+    points), an equal-weight star with zero-weight points among them (counts skip
+    them), and stars of varied weights (weight prefixes): both exact launches run on
+    the batch and every star matches the oracle."""
+    eq = synth.config1(3, start=11)
+    zero = synth.config1(1, start=12)
+    zero.w = zero.w.copy()
+    zero.w[::7] = 0.0   # every seventh point flagged
+    var = synth.varied_weights(3, start=2, max_sectors=3)
+    b = synth.concat([eq, zero, var])
+    _say("case mixed weight kinds exact: points", np.diff(b.offsets).tolist())
+    ds = pu.fetch(pu.run_gpu(b))
+    orc = pu.run_oracle(oracle, b)
+    worst = 0.0
+    for s in range(b.n_stars):
+        worst = max(worst, pu.compare_star(ds, orc, s, s, b.star(s), "mixed[%d]" % s)["max_rel_sr"])
+    _say("mixed weight kinds max rel SR err", worst)
 
 
 def test_varied_weights_packed(oracle):
