@@ -10,10 +10,12 @@
 // The constants' evaluation order is fixed (documented with the kernels' grid
 // formula) so the host and the device produce the same bits for f_i and nb_i.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <thread>
 #include <utility>
 
 #include "plan.hpp"
@@ -164,16 +166,46 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
 
   const double ksun = k_sun();
   std::vector<double>& gap_steps = plan->gap_steps;
-  int64_t off = 0;
+  // Offsets of the stars' points; the first star with an impossible point count
+  // ends the plan there (stars after it are not read).
+  int32_t n_valid = n_stars;
+  std::vector<int64_t> poff;
+  try {
+    poff.assign(n_stars + 1, 0);
+  } catch (...) {
+    delete plan;
+    return BLS_E_NOMEM;
+  }
   for (int32_t s = 0; s < n_stars; ++s) {
+    const int64_t n = stars[s].n_points;
+    if (n < 2 || n > kMaxPoints) {
+      n_valid = s;
+      break;
+    }
+    poff[s + 1] = poff[s] + n;
+  }
+  // Per star (independent, on host threads): checks of its points, its period
+  // range, grid, fine bins and gap list.  The results are then taken in star
+  // order, so the plan and the first failing star reported do not depend on the
+  // number of threads.
+  struct StarOut {
+    bls_status status = BLS_OK;
+    bool big = false, wide = false, dform = false;
+    std::vector<std::pair<double, int32_t>> gaps;
+  };
+  std::vector<StarOut> outs;
+  try {
+    outs.resize(n_valid);
+  } catch (...) {
+    delete plan;
+    return BLS_E_NOMEM;
+  }
+  auto star_work = [&](int32_t s) -> bls_status {
     const bls_star& st = stars[s];
-    auto fail = [&](bls_status code) {
-      if (bad_star) *bad_star = s;
-      delete plan;
-      return code;
-    };
+    StarOut& o = outs[s];
+    const int64_t off = poff[s];
+    auto fail = [](bls_status code) { return code; };
     const int64_t n = st.n_points;
-    if (n < 2 || n > kMaxPoints) return fail(n < 2 ? BLS_E_INPUT : BLS_E_UNSUPPORTED);
     const double* ts = t + off;
     const double* ws = w ? w + off : nullptr;
     const double* ys = y ? y + off : nullptr;
@@ -239,8 +271,8 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
       d.nb0 = fine_bins(d, plan->consts, u0 * u0);
     }
     if (nb_up > kNbWide || d.nb0 < 1) return fail(BLS_E_UNSUPPORTED);
-    if (nb_up > kNbLimit || d.n > plan->consts.big_points) plan->has_big = true;
-    if (nb_up > kNbLimitBig) plan->has_wide = true;
+    o.big = nb_up > kNbLimit || d.n > plan->consts.big_points;
+    o.wide = nb_up > kNbLimitBig;
     const int32_t sturges =
         static_cast<int32_t>(std::floor(1.0 + 3.322 * std::log10(static_cast<double>(d.nf)) + 0.5));
     d.sturges = std::max(1, std::min(sturges, kMaxSturges));
@@ -253,33 +285,71 @@ extern "C" bls_status bls_plan_create(const bls_params* p, int32_t n_stars, cons
     {
       const double fmax = freq_at(d, d.nf - 1);
       const double thr = gap_threshold(d, fmax, p->noverlap);
-      d.g_off = static_cast<int64_t>(plan->gaps.size());
-      try {
-        std::vector<std::pair<double, int32_t>> list;
-        for (int64_t i = 1; i < n; ++i)
-          if (ts[i] - ts[i - 1] >= thr) list.emplace_back(ts[i] - ts[i - 1], static_cast<int32_t>(i));
-        std::stable_sort(list.begin(), list.end(),
-                         [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
-                           return a.first > b.first;
-                         });
-        for (const auto& e : list) {
-          plan->gaps.push_back(e.second);
-          gap_steps.push_back(e.first);
-        }
-      } catch (...) {
-        return fail(BLS_E_NOMEM);
-      }
-      const int64_t ng = static_cast<int64_t>(plan->gaps.size()) - d.g_off;
-      if (ng > 0x7fffffff) return fail(BLS_E_UNSUPPORTED);
-      d.n_gaps = static_cast<int32_t>(ng);
-      if (ng > kGapLanes) plan->has_dform_star = true;
+      std::vector<std::pair<double, int32_t>>& list = o.gaps;
+      for (int64_t i = 1; i < n; ++i)
+        if (ts[i] - ts[i - 1] >= thr) list.emplace_back(ts[i] - ts[i - 1], static_cast<int32_t>(i));
+      std::stable_sort(list.begin(), list.end(),
+                       [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
+                         return a.first > b.first;
+                       });
+      if (static_cast<int64_t>(list.size()) > 0x7fffffff) return fail(BLS_E_UNSUPPORTED);
+      d.n_gaps = static_cast<int32_t>(list.size());
+      o.dform = d.n_gaps > kGapLanes;
     }
+    return BLS_OK;
+  };
+  {
+    const int64_t total = poff[n_valid];
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int32_t n_threads = total < (int64_t(1) << 20) ? 1 : static_cast<int32_t>(std::min<unsigned>({hw, 16u,
+                                                                    static_cast<unsigned>(std::max(1, n_valid))}));
+    std::atomic<int32_t> next{0};
+    auto worker = [&]() {
+      for (int32_t s; (s = next.fetch_add(1)) < n_valid;) {
+        try {
+          outs[s].status = star_work(s);
+        } catch (...) {
+          outs[s].status = BLS_E_NOMEM;
+        }
+      }
+    };
+    std::vector<std::thread> pool;
+    try {
+      for (int32_t k = 1; k < n_threads; ++k) pool.emplace_back(worker);
+    } catch (...) {
+      // fewer threads: the calling thread and those started share the stars
+    }
+    worker();
+    for (auto& th : pool) th.join();
+  }
+  for (int32_t s = 0; s < n_stars; ++s) {
+    auto fail = [&](bls_status code) {
+      if (bad_star) *bad_star = s;
+      delete plan;
+      return code;
+    };
+    if (s == n_valid) return fail(stars[s].n_points < 2 ? BLS_E_INPUT : BLS_E_UNSUPPORTED);
+    StarOut& o = outs[s];
+    if (o.status != BLS_OK) return fail(o.status);
+    StarDesc& d = plan->stars[s];
+    d.g_off = static_cast<int64_t>(plan->gaps.size());
+    try {
+      for (const auto& e : o.gaps) {
+        plan->gaps.push_back(e.second);
+        gap_steps.push_back(e.first);
+      }
+    } catch (...) {
+      return fail(BLS_E_NOMEM);
+    }
+    std::vector<std::pair<double, int32_t>>().swap(o.gaps);
+    if (o.big) plan->has_big = true;
+    if (o.wide) plan->has_wide = true;
+    if (o.dform) plan->has_dform_star = true;
     d.f_off = plan->n_freq;
     plan->n_freq += d.nf;
     plan->freq_offsets[s + 1] = plan->n_freq;
-    off += n;
   }
-  plan->n_points = off;
+  plan->n_points = poff[n_stars];
 
   // Work items: frequency tiles of each star sized to a similar number of cells
   // (points x frequencies), ordered by cost, largest first, so that the tail of

@@ -103,6 +103,33 @@ def test_invalid_inputs():
     _raises(-3, pmin=lambda a: a.__setitem__(0, 50.0))           # Pmin >= Pmax
 
 
+def test_first_failing_star_reported_from_threaded_plan():
+    """The per-star checks run on host threads for batches of more than 2^20 points;
+    the error returned is still that of the first failing star, whatever finishes
+    first, and a valid batch gives the same plan as its stars planned one by one."""
+    b = synth.concat([synth.config4(6, start=20), synth.config1(4, start=3)])
+    assert b.n_points > (1 << 20)
+    offs = b.offsets
+    t = b.t.copy()
+    t[offs[7] + 3] = t[offs[7] + 2] - 1.0      # star 7: times not sorted
+    t[offs[2] + 10] = np.nan                    # star 2: non-finite time
+    with pytest.raises(_lib.BlsError) as e:
+        _lib.Plan(t, b.y, b.w, b.offsets, b.rho, b.pmin, b.pmax)
+    assert e.value.code == -2 and e.value.star == 2
+    t = b.t.copy()
+    t[offs[7] + 3] = t[offs[7] + 2] - 1.0
+    with pytest.raises(_lib.BlsError) as e:
+        _lib.Plan(t, b.y, b.w, b.offsets, b.rho, b.pmin, b.pmax)
+    assert e.value.star == 7
+    whole = _lib.Plan(b.t, b.y, b.w, b.offsets, b.rho, b.pmin, b.pmax)
+    nf = np.diff(whole.freq_offsets)
+    for s in range(b.n_stars):
+        one = b.subset([s])
+        p1 = _lib.Plan(one.t, one.y, one.w, one.offsets, one.rho, one.pmin, one.pmax)
+        assert p1.n_freq == nf[s]
+        assert whole.star_info(s) == p1.star_info(0)
+
+
 def test_zero_weight_points_excluded_from_baseline(oracle):
     b = synth.ragged(1, start=2)
     t, y, w = b.star(0)
