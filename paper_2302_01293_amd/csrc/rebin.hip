@@ -17,14 +17,16 @@
 // every set of a frequency fits the 8192 accumulator pairs together, up to 32
 // frequencies are binned in one pass over the points (the phase once per point and
 // frequency, then one multiply and two LDS adds per set); otherwise one set at a
-// time, in passes over start-bin ranges beyond 8192 bins.  The best window over
-// (k, j) has the largest power; ties go to the smallest (k, j).
+// time, in passes over start-bin ranges beyond 8192 bins.  Stars of equal weights
+// add 32-bit counts of weighted points in place of weight prefixes (counts.hpp).
+// The best window over (k, j) has the largest power; ties go to the smallest (k, j).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
 
+#include "counts.hpp"
 #include "plan.hpp"
 
 namespace mi355bls {
@@ -35,6 +37,8 @@ constexpr int kRebinThreads = 1024;
 constexpr int kRebinSlots = 8192;      // int64 accumulator pairs (128 KiB)
 constexpr int kRebinF = 32;            // most frequencies binned together
 constexpr int kScanIter = kRebinSlots / kRebinThreads;
+static_assert((kRebinF & (kRebinF - 1)) == 0 && (kRebinMax & (kRebinMax - 1)) == 0 && kRebinMax <= 64 && kRebinF <= 64,
+              "rows of the set tables are read one entry per lane");
 constexpr double kUnitW = 2.168404344971008868e-19;  // 2^-62: one fixed-point weight unit
 
 struct RebinArgs {
@@ -68,6 +72,13 @@ struct RebinLds {
   double ws[kRebinThreads / 64];
 };
 
+__device__ __forceinline__ double readlane_f64(double v, int src) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(bits), src);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(bits >> 32), src);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 struct Cand {
   unsigned long long key;  // bits of the power + 1 (0: none); powers are >= 0
   uint32_t kj;             // (k << 20) | j
@@ -78,16 +89,46 @@ __device__ __forceinline__ bool cand_better(const Cand& a, const Cand& b) {
   return a.key > b.key || (a.key == b.key && a.key != 0ull && a.kj < b.kj);
 }
 
-// Time of point q and the exclusive prefix sums of the fixed-point weights and
-// weighted residuals at q and q + 1 (the star's totals after its last point).
+// The weight side of a star: prefixes of the fixed-point weights, or (equal
+// weights, cnt) counts of weighted points, the prefixes divided by `unit`.
+struct WeightForm {
+  bool cnt;
+  CountDiv cd;
+  int64_t unit;
+  long long total;  // the star's total in the form's units
+};
+
+__device__ __forceinline__ WeightForm weight_form(const StarRt& rt) {
+  WeightForm wf;
+  wf.cnt = rt.w_unit != 0;
+  wf.unit = rt.w_unit;
+  wf.cd = wf.cnt ? count_div(rt.w_unit) : CountDiv{0u, 0u};
+  wf.total = wf.cnt ? static_cast<long long>(count_of(rt.cw_total, wf.cd)) : rt.cw_total;
+  return wf;
+}
+
+// Time of point q and the exclusive prefix sums of the weights (in the form's
+// units) and weighted residuals at q and q + 1 (the star's totals after its last
+// point).
 __device__ __forceinline__ void point_prefix(const double* __restrict__ dt, const int64_t* __restrict__ cw,
-                                             const int64_t* __restrict__ cs, const StarRt& rt, int64_t q, int64_t n,
-                                             double& x, long long& p0, long long& p1, long long& s0, long long& s1) {
+                                             const int64_t* __restrict__ cs, const StarRt& rt, const WeightForm& wf,
+                                             int64_t q, int64_t n, double& x, long long& p0, long long& p1,
+                                             long long& s0, long long& s1) {
   x = dt[q];
   p0 = cw[q];
   s0 = cs[q];
   p1 = q + 1 < n ? cw[q + 1] : rt.cw_total;
   s1 = q + 1 < n ? cs[q + 1] : rt.cs_total;
+  if (wf.cnt) {
+    p0 = count_of(p0, wf.cd);
+    p1 = q + 1 < n ? static_cast<long long>(count_of(p1, wf.cd)) : wf.total;
+  }
+}
+
+// A window's weight total in fixed-point units from the sum of its slots (counts:
+// each slot's low word is its bin's count, the high word stays zero).
+__device__ __forceinline__ unsigned long long weight_units(unsigned long long rw, const WeightForm& wf) {
+  return wf.cnt ? rw * static_cast<unsigned long long>(wf.unit) : rw;
 }
 
 // Adds one wave's 64 consecutive points (one set of one frequency) to the LDS
@@ -98,7 +139,7 @@ __device__ __forceinline__ void point_prefix(const double* __restrict__ dt, cons
 // a run on one address.  The chunk's first and last points close their runs, so
 // chunks are independent.  The neighbours' bins come by DPP wave shifts.
 // slot < 0: the point's bin is not held.
-__device__ __forceinline__ void add_chunk(RebinLds& L, int lane, int last, bool valid, int32_t b, int slot,
+__device__ __forceinline__ void add_chunk(RebinLds& L, bool cnt, int lane, int last, bool valid, int32_t b, int slot,
                                           long long p0, long long p1, long long s0, long long s1) {
   const int32_t bp = __builtin_amdgcn_update_dpp(b, b, 0x138, 0xf, 0xf, false);  // lane - 1 (wave_shr:1)
   const int32_t bn = __builtin_amdgcn_update_dpp(b, b, 0x130, 0xf, 0xf, false);  // lane + 1 (wave_shl:1)
@@ -109,7 +150,10 @@ __device__ __forceinline__ void add_chunk(RebinLds& L, int lane, int last, bool 
                                   (start ? static_cast<unsigned long long>(p0) : 0ull);
     const unsigned long long vs = (end ? static_cast<unsigned long long>(s1) : 0ull) -
                                   (start ? static_cast<unsigned long long>(s0) : 0ull);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&L.gw[slot]), vw);
+    if (cnt)  // the low word of the slot
+      atomicAdd(reinterpret_cast<unsigned int*>(&L.gw[slot]), static_cast<unsigned int>(vw));
+    else
+      atomicAdd(reinterpret_cast<unsigned long long*>(&L.gw[slot]), vw);
     atomicAdd(reinterpret_cast<unsigned long long*>(&L.gs[slot]), vs);
   }
 }
@@ -148,9 +192,9 @@ __device__ __forceinline__ void write_best(const RebinArgs& a, int64_t out, unsi
 // One frequency whose bin sets do not fit together: one set at a time, in passes
 // over ranges of start bins when a set exceeds the accumulators.
 template <bool DIP>
-__device__ void rebin_one(const RebinArgs& a, RebinLds& L, const StarDesc& d, const StarRt& rt, int64_t fi,
-                          const double* __restrict__ dt, const int64_t* __restrict__ cw,
-                          const int64_t* __restrict__ cs) {
+__device__ void rebin_one(const RebinArgs& a, RebinLds& L, const StarDesc& d, const StarRt& rt,
+                          const WeightForm& wf, int64_t fi, const double* __restrict__ dt,
+                          const int64_t* __restrict__ cw, const int64_t* __restrict__ cs) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, T = kRebinThreads;
   const int32_t nov = a.c.noverlap;
   const int64_t n = d.n;
@@ -181,13 +225,13 @@ __device__ void rebin_one(const RebinArgs& a, RebinLds& L, const StarDesc& d, co
         const int last = static_cast<int>(min<int64_t>(63, n - 1 - c0));
         long long p0 = 0, p1 = 0, s0 = 0, s1 = 0;
         double x = 0.0;
-        if (valid) point_prefix(dt, cw, cs, rt, q, n, x, p0, p1, s0, s1);
+        if (valid) point_prefix(dt, cw, cs, rt, wf, q, n, x, p0, p1, s0, s1);
         const double ph = __builtin_amdgcn_fract(x * f);  // x - floor(x)
         int32_t b = static_cast<int32_t>(ph * nbd);
         b = b < nb - 1 ? b : nb - 1;
         int32_t slot = b - b0;
         if (slot < 0) slot += nb;
-        add_chunk(L, lane, last, valid, b, slot < nslot ? slot : -1, p0, p1, s0, s1);
+        add_chunk(L, wf.cnt, lane, last, valid, b, slot < nslot ? slot : -1, p0, p1, s0, s1);
       }
       __syncthreads();
       for (int j = tid; j < span && b0 + j < nb; j += T) {
@@ -199,7 +243,7 @@ __device__ void rebin_one(const RebinArgs& a, RebinLds& L, const StarDesc& d, co
           rs += static_cast<unsigned long long>(L.gs[idx]);
         }
         double r, s;
-        const unsigned long long key = window_key<DIP>(rw, rs, rt.s_scale, r, s);
+        const unsigned long long key = window_key<DIP>(weight_units(rw, wf), rs, rt.s_scale, r, s);
         if (key > mine.key) {  // k, then j, ascend within a thread: ties keep the first
           mine.key = key;
           mine.kj = (static_cast<uint32_t>(k) << 20) | static_cast<uint32_t>(b0 + j);
@@ -245,9 +289,9 @@ __device__ void rebin_one(const RebinArgs& a, RebinLds& L, const StarDesc& d, co
 // One pass over the points bins each point's phase into every set.  Returns the
 // number of frequencies searched (0: the first does not fit; use rebin_one).
 template <bool DIP>
-__device__ int rebin_group(const RebinArgs& a, RebinLds& L, const StarDesc& d, const StarRt& rt, int64_t g0,
-                           int64_t g_end, const double* __restrict__ dt, const int64_t* __restrict__ cw,
-                           const int64_t* __restrict__ cs) {
+__device__ int rebin_group(const RebinArgs& a, RebinLds& L, const StarDesc& d, const StarRt& rt,
+                           const WeightForm& wf, int64_t g0, int64_t g_end, const double* __restrict__ dt,
+                           const int64_t* __restrict__ cw, const int64_t* __restrict__ cs) {
   const int tid = threadIdx.x, T = kRebinThreads;
   const int32_t nov = a.c.noverlap, K = a.c.n_rebin;
   const int64_t n = d.n;
@@ -294,22 +338,28 @@ __device__ int rebin_group(const RebinArgs& a, RebinLds& L, const StarDesc& d, c
   }
   __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
+  // The group's frequencies and, per frequency, its sets' bins and first slots are
+  // read from LDS once per 64-point chunk as a row across the lanes (lane i holds
+  // entry i; entries past F or K are in bounds and unused), then taken lane by lane
+  // into scalar registers: one LDS read per frequency instead of one per set.
+  const double f_row = L.f[lane & (kRebinF - 1)];
   for (int64_t c0 = static_cast<int64_t>(wave) * 64; c0 < n; c0 += static_cast<int64_t>(T)) {
     const int64_t q = c0 + lane;
     const bool valid = q < n;
     const int last = static_cast<int>(min<int64_t>(63, n - 1 - c0));
     long long p0 = 0, p1 = 0, s0 = 0, s1 = 0;
     double x = 0.0;
-    if (valid) point_prefix(dt, cw, cs, rt, q, n, x, p0, p1, s0, s1);
+    if (valid) point_prefix(dt, cw, cs, rt, wf, q, n, x, p0, p1, s0, s1);
     for (int fi = 0; fi < F; ++fi) {
-      const double ph = __builtin_amdgcn_fract(x * L.f[fi]);  // x - floor(x)
+      const double ph = __builtin_amdgcn_fract(x * readlane_f64(f_row, fi));  // x - floor(x)
+      const int2 row = L.nbo[fi][lane & (kRebinMax - 1)];
       for (int k = 0; k < K; ++k) {
-        const int2 nbo = L.nbo[fi][k];
-        const int32_t nb = nbo.x;
+        const int32_t nb = __builtin_amdgcn_readlane(row.x, k);
         if (nb == 0) continue;
+        const int32_t slot0 = __builtin_amdgcn_readlane(row.y, k);
         int32_t b = static_cast<int32_t>(ph * static_cast<double>(nb));
         b = b < nb - 1 ? b : nb - 1;
-        add_chunk(L, lane, last, valid, b, nbo.y + b, p0, p1, s0, s1);
+        add_chunk(L, wf.cnt, lane, last, valid, b, slot0 + b, p0, p1, s0, s1);
       }
     }
   }
@@ -341,7 +391,7 @@ __device__ int rebin_group(const RebinArgs& a, RebinLds& L, const StarDesc& d, c
           rs += static_cast<unsigned long long>(L.gs[sb + idx]);
         }
         double r, s;
-        const unsigned long long key = window_key<DIP>(rw, rs, rt.s_scale, r, s);
+        const unsigned long long key = window_key<DIP>(weight_units(rw, wf), rs, rt.s_scale, r, s);
         if (key != 0ull) {
           ckey[it] = key;
           ckj[it] = (static_cast<uint32_t>(k) << 20) | static_cast<uint32_t>(j);
@@ -371,7 +421,7 @@ __device__ int rebin_group(const RebinArgs& a, RebinLds& L, const StarDesc& d, c
         rw += static_cast<unsigned long long>(L.gw[sb + idx]);
         rs += static_cast<unsigned long long>(L.gs[sb + idx]);
       }
-      (void)window_key<DIP>(rw, rs, rt.s_scale, r, s);
+      (void)window_key<DIP>(weight_units(rw, wf), rs, rt.s_scale, r, s);
     }
     write_best(a, d.f_off + g0 + tid, key, kj, r, s);
   }
@@ -399,15 +449,16 @@ __global__ void __launch_bounds__(kRebinThreads) k_search_rebin(RebinArgs a) {
     i0 = max<int64_t>(0, min<int64_t>(i0, d.nf));
     i1 = max<int64_t>(0, min<int64_t>(i1, d.nf));
     const StarRt rt = a.rt[star];
+    const WeightForm wf = weight_form(rt);
     const double* __restrict__ dt = a.dt + d.p_off;
     const int64_t* __restrict__ cw = a.cw + d.p_off;
     const int64_t* __restrict__ cs = a.cs + d.p_off;
     for (int64_t g0 = i0; g0 < i1;) {
-      const int F = rebin_group<DIP>(a, L, d, rt, g0, i1, dt, cw, cs);
+      const int F = rebin_group<DIP>(a, L, d, rt, wf, g0, i1, dt, cw, cs);
       if (F > 0) {
         g0 += F;
       } else {
-        rebin_one<DIP>(a, L, d, rt, g0, dt, cw, cs);
+        rebin_one<DIP>(a, L, d, rt, wf, g0, dt, cw, cs);
         g0 += 1;
       }
     }

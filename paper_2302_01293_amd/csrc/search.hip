@@ -35,6 +35,7 @@
 #include <cstdint>
 #include <type_traits>
 
+#include "counts.hpp"
 #include "plan.hpp"
 
 namespace mi355bls {
@@ -396,28 +397,6 @@ __device__ __forceinline__ void lds_add64(unsigned char* base, uint32_t byte_off
 
 __device__ __forceinline__ void lds_sub64(unsigned char* base, uint32_t byte_off, uint32_t v) {
   atomicAdd(reinterpret_cast<unsigned int*>(base + byte_off), 0u - v);
-}
-
-// Exact division of a weight prefix v = count * unit by the star's common weight
-// (count < 2^32): with unit = 2^shift * odd, v >> shift = count * odd, and
-// multiplying by the inverse of odd modulo 2^32 leaves count modulo 2^32, which is
-// count.  The inverse comes from Newton's iteration x <- x (2 - odd x), which
-// doubles the number of correct low bits from the 3 of x = odd.
-struct CountDiv {
-  uint32_t shift, inv;
-};
-
-__device__ __forceinline__ CountDiv count_div(int64_t unit) {
-  const uint64_t u = static_cast<uint64_t>(unit);
-  const uint32_t t = static_cast<uint32_t>(__builtin_ctzll(u));
-  const uint32_t odd = static_cast<uint32_t>(u >> t);
-  uint32_t x = odd;
-  for (int i = 0; i < 4; ++i) x *= 2u - odd * x;
-  return CountDiv{t, x};
-}
-
-__device__ __forceinline__ uint32_t count_of(long long v, CountDiv c) {
-  return static_cast<uint32_t>(static_cast<uint64_t>(v) >> c.shift) * c.inv;
 }
 
 // Slot index -> (frequency k, bin b) for idx < F * stride <= 4096: a float
