@@ -48,8 +48,8 @@ def search_sources_digest() -> str:
     import hashlib
     import re
     h = hashlib.sha256()
-    for rel in ("paper_2302_01293_amd/csrc/search.hip", "paper_2302_01293_amd/csrc/plan.hpp",
-                "paper_2302_01293_amd/csrc/plan.cpp"):
+    for rel in ("paper_2302_01293_amd/csrc/search.hip", "paper_2302_01293_amd/csrc/counts.hpp",
+                "paper_2302_01293_amd/csrc/plan.hpp", "paper_2302_01293_amd/csrc/plan.cpp"):
         with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
             text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
         for line in text.splitlines():
