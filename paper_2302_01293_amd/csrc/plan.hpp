@@ -23,16 +23,19 @@ constexpr int kThreads = 1024;        // threads per preparation / resampling wo
 constexpr int kSnrThreads = 256;      // threads per S/N workgroup for short spectra
 constexpr int64_t kSnrSmallMaxFreqs = 32768;  // longest spectrum of such a batch
 constexpr int kSearchThreads = 512;   // threads per search workgroup
-// Two shapes of the one-pass search workgroup.  The common one: 48 KB of
-// per-frequency accumulators, 8 register-resident points per thread and at most 80
-// registers per lane, three workgroups per CU (6 waves per SIMD).  The large one,
-// for frequencies with more fine bins: 72 KB, 12 points, 128 registers, two per CU.
+// Two shapes of the one-pass search workgroup.  The common one: 512 threads, 48 KB
+// of per-frequency accumulators, 8 register-resident points per thread and at most
+// 80 registers per lane, three workgroups per CU (6 waves per SIMD).  The large one,
+// for frequencies with more fine bins: 768 threads, 72 KB, 8 points, 80 registers,
+// two per CU (also 6 waves per SIMD).
 constexpr int kGBytes = 48 * 1024;
 constexpr int kUMaxSmall = 8;
 constexpr int kSearchGroupsPerCu = 3;
 constexpr int kGBytesBig = 72 * 1024;
-constexpr int kUMax = 12;             // register-resident points per thread, at most
+constexpr int kUMax = 12;             // register-resident points per thread of k_search_wide
 constexpr int kSearchGroupsPerCuBig = 2;
+constexpr int kSearchThreadsBig = 768;   // large-shape workgroup (12 waves; 6 per SIMD at two per CU)
+constexpr int kUMaxBig = 8;              // its register-resident points per thread
 constexpr int kNbLimit = kGBytes / 16 - 32;        // largest fine-bin count of the common
                                                     // shape (16 B per bin, plus the
                                                     // replicated wrap bins): 3040

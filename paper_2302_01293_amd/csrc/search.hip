@@ -301,17 +301,21 @@ struct Win {
   static constexpr int bytes = BIG ? kGBytesBig : kGBytes;
   static constexpr int arr_bytes = bytes / 2;                // per array (G_W, G_S)
   static constexpr int elems = arr_bytes / 8;                // F * stride <= elems
-  static constexpr int slot_iter = elems / kSearchThreads;   // slots per thread (scan)
+  static constexpr int threads = BIG ? kSearchThreadsBig : kSearchThreads;
+  static constexpr int slot_iter = (elems + threads - 1) / threads;  // slots per thread (scan)
   static constexpr int nb_lo = BIG ? kNbLimit : 0;
   static constexpr int nb_hi = BIG ? kNbLimitBig : kNbLimit;
   static constexpr int groups = BIG ? kSearchGroupsPerCuBig : kSearchGroupsPerCu;
-  static constexpr int um = BIG ? kUMax : kUMaxSmall;        // register points per thread
+  static constexpr int um = BIG ? kUMaxBig : kUMaxSmall;     // register points per thread
 };
-static_assert(kUMax % kUGroup == 0 && kUMaxSmall % kUGroup == 0, "the folds take whole groups of steps");
+static_assert(kUMax % kUGroup == 0 && kUMaxSmall % kUGroup == 0 && kUMaxBig % kUGroup == 0,
+              "the folds take whole groups of steps");
 // A large-shape group of a star that is not long holds one frequency (two with
 // more than kNbLimit bins do not fit), so it never reaches frequencies of the
 // common shape.
 static_assert(2 * (kNbLimit + 1) > Win<true>::elems, "one frequency per large-shape group");
+// Scan slots per thread of k_search_wide (512 threads over the large window).
+constexpr int kWideSlotIter = (Win<true>::elems + kSearchThreads - 1) / kSearchThreads;
 
 struct SearchArgs {
   const StarDesc* stars;
@@ -822,10 +826,10 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
       __syncthreads();
     }
     // scan of the windows starting in [b0, b0 + span)
-    unsigned long long skey[Win<true>::slot_iter];
-    uint32_t smj[Win<true>::slot_iter];
+    unsigned long long skey[kWideSlotIter];
+    uint32_t smj[kWideSlotIter];
 #pragma unroll
-    for (int r = 0; r < Win<true>::slot_iter; ++r) {
+    for (int r = 0; r < kWideSlotIter; ++r) {
       const int j = tid + r * T;
       skey[r] = 0ull;
       smj[r] = ~0u;
@@ -856,7 +860,7 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < Win<true>::slot_iter; ++r)
+    for (int r = 0; r < kWideSlotIter; ++r)
       if (skey[r] != 0ull && skey[r] == g->key[0]) atomicMin(&g->mj[0], smj[r]);
     __syncthreads();
     if (tid == 0) {
@@ -905,7 +909,7 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
 // the frequencies whose fine-bin count lies in (kNbLimit, kNbLimitBig] and for every
 // frequency up to kNbLimitBig bins of stars with more than big_points points.
 template <bool PACKED, bool DFORM, bool DIP, bool BIG, bool EXQ, bool CNT>
-__global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search(SearchArgs a) {
+__global__ void __launch_bounds__(Win<BIG>::threads, Win<BIG>::groups * Win<BIG>::threads / 256) k_search(SearchArgs a) {
   static_assert(!CNT || (!PACKED && !DFORM), "counts replace the weight prefixes of the exact telescoping form");
   using W = Win<BIG>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -917,7 +921,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int T = kSearchThreads;
+  const int T = W::threads;
   const int m_max = a.c.m_max;
   const uint32_t m_mask = a.c.m_mask;
 
@@ -971,7 +975,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
     // stay coalesced and the boundaries of one step fall on consecutive bins.
     // The difference form keeps fewer points in registers (its fold holds more
     // values per boundary).
-    constexpr int UM = DFORM ? (BIG ? 8 : 4) : W::um;
+    constexpr int UM = DFORM ? 4 : W::um;
     static_assert(UM % kUGroup == 0, "the fold takes whole groups of steps");
     const int nchunks = static_cast<int>((n + static_cast<int64_t>(T) * UM - 1) / (static_cast<int64_t>(T) * UM));
     const int run = static_cast<int>((n + static_cast<int64_t>(T) * nchunks - 1) / (static_cast<int64_t>(T) * nchunks));
@@ -1071,7 +1075,7 @@ __global__ void __launch_bounds__(kSearchThreads, 2 * Win<BIG>::groups) k_search
       // bin is still unconverted then (a wave's LDS accesses run in program order);
       // G[0] is read before chunk 0 is written.  The result goes to FP64 with the
       // first bins replicated after the last (windows wrap past nb - 1).
-      for (int k = __builtin_amdgcn_readfirstlane(wave); k < F; k += kSearchThreads / 64) {
+      for (int k = __builtin_amdgcn_readfirstlane(wave); k < F; k += W::threads / 64) {
         const int32_t nb = __builtin_amdgcn_readfirstlane(g->nb[k]);
         const int32_t bl = g->blast[k];
         const int mrep = min(m_max, nb - 1);
@@ -1380,7 +1384,7 @@ template <bool BIG>
 static void launch_search(bool packed, int form, bool dip, bool exq, int64_t n_items, int cus, hipStream_t st,
                           const SearchArgs& a) {
   const int64_t grid = std::min<int64_t>(n_items, Win<BIG>::groups * static_cast<int64_t>(cus));
-  const dim3 gd(static_cast<unsigned>(grid)), bd(kSearchThreads);
+  const dim3 gd(static_cast<unsigned>(grid)), bd(Win<BIG>::threads);
   const size_t lds = search_lds<BIG>();
   if (exq)
     launch_search_x<BIG, true>(packed, form, dip, gd, bd, lds, st, a);
