@@ -24,7 +24,9 @@
 //    subtracts them from the bin it leaves.  Integer sums are exact, so the
 //    result does not depend on order.
 //  * Points stay in registers (dt, CW, CS) across all frequencies of a work item;
-//    only boundaries touch LDS (one 64-bit integer atomic pair per boundary).
+//    only boundaries touch LDS (one 64-bit integer atomic pair per boundary, or,
+//    for stars of equal weights, a 32-bit count of weighted points in place of the
+//    weight prefix: counts.hpp).
 //  * The phase frac((t - t0) f) is computed in FP64 with the same IEEE operations
 //    as the grid (this file is compiled with -ffp-contract=off), so the bin of
 //    every point is bit-identical to a sequential FP64 evaluation.
