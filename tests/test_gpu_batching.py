@@ -72,10 +72,18 @@ def test_pipeline_graph_with_copies_matches_eager():
         torch.cuda.synchronize()
 
 
-def test_windows_match_full_grid():
+@pytest.mark.parametrize("kind", ["equal", "mixed"])
+def test_windows_match_full_grid(kind):
+    """Caller windows give the full search's results bit for bit on the frequencies
+    they cover and leave the rest untouched; "mixed" holds stars of equal weights
+    (counts of weighted points) and of varied weights (weight prefixes), so both
+    exact launches serve the windows."""
     import torch
-    b = synth.ragged(5, start=80)
-    _say("case windows: 5 ragged stars")
+    if kind == "equal":
+        b = synth.ragged(5, start=80)
+    else:
+        b = synth.concat([synth.ragged(3, start=80), synth.varied_weights(2, start=4, max_sectors=2)])
+    _say("case windows (%s weights): 5 stars" % kind)
     ds = pu.run_gpu(b)
     full = ds.sr_host()
     best_full = ds.best_host().copy()
