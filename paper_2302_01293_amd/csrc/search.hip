@@ -912,7 +912,7 @@ __device__ void wide_frequency(unsigned char* smem, GroupLds* g, const SearchArg
 // frequency up to kNbLimitBig bins of stars with more than big_points points.
 template <bool PACKED, bool DFORM, bool DIP, bool BIG, bool EXQ, bool CNT>
 __global__ void __launch_bounds__(Win<BIG>::threads, Win<BIG>::groups * Win<BIG>::threads / 256) k_search(SearchArgs a) {
-  static_assert(!CNT || (!PACKED && !DFORM), "counts replace the weight prefixes of the exact telescoping form");
+  static_assert(!CNT || !PACKED, "counts replace the weight prefixes of the exact sums");
   using W = Win<BIG>;
   extern __shared__ __align__(16) unsigned char smem[];
   long long* GW = reinterpret_cast<long long*>(smem);
@@ -927,10 +927,10 @@ __global__ void __launch_bounds__(Win<BIG>::threads, Win<BIG>::groups * Win<BIG>
   const int m_max = a.c.m_max;
   const uint32_t m_mask = a.c.m_mask;
 
-  // Exact telescoping form: the stars of equal weights (counts) and the others run
-  // in separate launches; k_prepare flags which kinds the batch holds, so a launch
-  // with nothing to do ends here.
-  if constexpr (!PACKED && !DFORM) {
+  // Exact sums: the stars of equal weights (counts) and the others run in separate
+  // launches; k_prepare flags which kinds the batch holds, so a launch with nothing
+  // to do ends here.
+  if constexpr (!PACKED) {
     if ((a.next[kFlagsIndex] & (CNT ? kHasEqualWeights : kHasUnequalWeights)) == 0u) return;
   }
   int queue = static_cast<int>(blockIdx.x % kXcds);  // used by thread 0 only
@@ -950,7 +950,7 @@ __global__ void __launch_bounds__(Win<BIG>::threads, Win<BIG>::groups * Win<BIG>
     // Equal weights: CW[n] is the common weight times the number of weighted points
     // before n, so G_W accumulates those counts in 32 bits (telescoped differences
     // are exact modulo 2^32, every count is below 2^31) and H_W is rebuilt from them.
-    if constexpr (!PACKED && !DFORM) {
+    if constexpr (!PACKED) {
       if ((rt.w_unit != 0) != CNT) continue;  // the other launch's star
     }
     constexpr bool cnt = CNT;
@@ -1361,8 +1361,8 @@ static void launch_k(bool dip, const dim3& gd, const dim3& bd, size_t lds, hipSt
 }
 
 // Accumulation forms of one launch: telescoping with weight prefixes, difference
-// form, telescoping with counts of weighted points (precision 0, equal weights).
-enum SearchForm { kFormPrefix = 0, kFormDiff = 1, kFormCount = 2 };
+// form, and both with counts of weighted points (precision 0, equal weights).
+enum SearchForm { kFormPrefix = 0, kFormDiff = 1, kFormCount = 2, kFormDiffCount = 3 };
 
 template <bool BIG, bool EXQ>
 static void launch_search_x(bool packed, int form, bool dip, const dim3& gd, const dim3& bd, size_t lds,
@@ -1372,6 +1372,8 @@ static void launch_search_x(bool packed, int form, bool dip, const dim3& gd, con
     else launch_k<true, false, BIG, EXQ, false>(dip, gd, bd, lds, st, a);
   } else if (form == kFormDiff) {
     launch_k<false, true, BIG, EXQ, false>(dip, gd, bd, lds, st, a);
+  } else if (form == kFormDiffCount) {
+    launch_k<false, true, BIG, EXQ, true>(dip, gd, bd, lds, st, a);
   } else if (form == kFormCount) {
     launch_k<false, false, BIG, EXQ, true>(dip, gd, bd, lds, st, a);
   } else {
@@ -1431,13 +1433,15 @@ extern "C" bls_status bls_search_batch(bls_plan* plan, void* ws, const int64_t* 
   // frequencies beyond one LDS pass.  Per shape: stars of equal weights with counts
   // (precision 0; a launch ends at once when the batch has none, and likewise the
   // next one when every star has equal weights), the other stars, and (when the
-  // batch needs it) stars whose steps mostly skip fine bins in difference form.
+  // batch needs it) stars whose steps mostly skip fine bins in difference form, again
+  // with counts and then with weight prefixes.
   // Each launch skips the others' work.
   const bool packed = plan->consts.packed != 0, dip = a.c.dip_only != 0, exq = a.c.exact_q != 0;
   const bool dform = d_windows ? plan->has_dform_star : plan->has_dform;
-  int forms[3], n_forms = 0;
+  int forms[4], n_forms = 0;
   if (!packed) forms[n_forms++] = kFormCount;
   forms[n_forms++] = kFormPrefix;
+  if (dform && !packed) forms[n_forms++] = kFormDiffCount;
   if (dform) forms[n_forms++] = kFormDiff;
   for (int big = 0; big < (plan->has_big ? 2 : 1); ++big) {
     for (int fi = 0; fi < n_forms; ++fi) {
